@@ -1,0 +1,219 @@
+"""FP64 CPU oracle: ctypes binding of nellox_oracle.c plus a torch-FP64 reference.
+
+TEST INFRASTRUCTURE ONLY. The product (the HIP library and its Python
+binding) never imports this package; only tests, the smoke check and the
+benchmark's CPU-baseline leg do. It shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nellox_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+E_NAN = -5
+E_CDF = -6
+E_CORRUPT = -4
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C99, -O2)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, I, D, L64, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_size_t
+        L.ox_model_new.restype = P
+        L.ox_model_new.argtypes = [I, I, I, P]
+        L.ox_model_from_blob.restype = P
+        L.ox_model_from_blob.argtypes = [P, S, P, P]
+        L.ox_model_free.argtypes = [P]
+        L.ox_param_count.restype = L64
+        L.ox_param_count.argtypes = [I, I, I]
+        L.ox_stats.restype = I
+        L.ox_stats.argtypes = [P, P, I, I, I, I, P, P, P]
+        L.ox_theta_image.restype = I
+        L.ox_theta_image.argtypes = [P, P, I, I, P]
+        L.ox_encode.restype = L64
+        L.ox_encode.argtypes = [P, P, I, I, I, I, I, P, S]
+        L.ox_decode.restype = I
+        L.ox_decode.argtypes = [P, P, S, I, I, I, I, I, P]
+        L.ox_rans_encode.restype = L64
+        L.ox_rans_encode.argtypes = [P, P, L64, P, S]
+        L.ox_rans_decode.restype = L64
+        L.ox_rans_decode.argtypes = [P, L64, P, S, P]
+        L.ox_encode_offset.restype = L64
+        L.ox_encode_offset.argtypes = [P, P, I, I, I, I, I, P, S]
+        L.ox_decode_offset.restype = I
+        L.ox_decode_offset.argtypes = [P, P, S, I, I, I, I, I, P]
+        L.ox_symbol_order.restype = L64
+        L.ox_symbol_order.argtypes = [I, I, I, P]
+        L.ox_tap_live.restype = I
+        L.ox_tap_live.argtypes = [I, I, I]
+        L.ox_steps.restype = L64
+        L.ox_steps.argtypes = [I, I, I]
+        L.ox_lane_count.restype = I
+        L.ox_lane_count.argtypes = [I, I, I, I]
+        L.ox_log_bin.restype = D
+        L.ox_log_bin.argtypes = [I, D, D]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with code {code}")
+        self.code = code
+
+
+class Model:
+    """An FP64 oracle model (its own copy of the parameters, double precision)."""
+
+    def __init__(self, handle, dims):
+        self._h = handle
+        self.h, self.C, self.n_blocks = dims
+
+    @classmethod
+    def from_blob(cls, blob: bytes) -> "Model":
+        L = lib()
+        dims = np.zeros(3, dtype=np.int32)
+        hsh = np.zeros(1, dtype=np.uint64)
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        h = L.ox_model_from_blob(_ptr(buf), buf.size, _ptr(dims), _ptr(hsh))
+        if not h:
+            raise ValueError("oracle rejected the weight blob")
+        m = cls(h, tuple(int(x) for x in dims))
+        m.hash = int(hsh[0])
+        return m
+
+    @classmethod
+    def from_params(cls, h: int, C: int, n_blocks: int, params) -> "Model":
+        L = lib()
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        if p.size != L.ox_param_count(h, C, n_blocks):
+            raise ValueError("parameter count does not match dims")
+        hd = L.ox_model_new(h, C, n_blocks, _ptr(p))
+        if not hd:
+            raise ValueError("bad dims")
+        return cls(hd, (h, C, n_blocks))
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().ox_model_free(self._h)
+        except Exception:
+            pass
+
+    # -- statistics -------------------------------------------------------
+    def stats(self, img: np.ndarray, ph: int = 0, pw: int = 0, cdf: bool = False, px_bits: bool = False):
+        """Returns dict(qbits, cbits[, cdf (H,W,3,257) int32][, px_bits (H,W)])."""
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        H, W, _ = img.shape
+        out = np.zeros(2, dtype=np.float64)
+        cd = np.zeros((H, W, 3, 257), dtype=np.int32) if cdf else None
+        pb = np.zeros((H, W), dtype=np.float64) if px_bits else None
+        rc = lib().ox_stats(self._h, _ptr(img), H, W, ph, pw, _ptr(out),
+                            _ptr(cd) if cd is not None else None, _ptr(pb) if pb is not None else None)
+        if rc:
+            raise OracleError(rc, "stats")
+        r = dict(qbits=float(out[0]), cbits=float(out[1]))
+        if cd is not None:
+            r["cdf"] = cd
+        if pb is not None:
+            r["px_bits"] = pb
+        return r
+
+    def theta_image(self, img: np.ndarray) -> np.ndarray:
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        H, W, _ = img.shape
+        th = np.zeros((H, W, 100), dtype=np.float64)
+        rc = lib().ox_theta_image(self._h, _ptr(img), H, W, _ptr(th))
+        if rc:
+            raise OracleError(rc, "theta")
+        return th
+
+    # -- codec ------------------------------------------------------------
+    def encode(self, img: np.ndarray, order: int = 0, ph: int = 0, pw: int = 0,
+               offset: int | None = None) -> bytes:
+        """order 0 raster, 1 wavefront (step j + (h+1) i); `offset` overrides
+        the wavefront step offset (tests of non-causal orders)."""
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        H, W, _ = img.shape
+        cap = 64 + 8 * H * W * 3 + 16 * lib().ox_lane_count(H, W, ph, pw)
+        out = np.zeros(cap, dtype=np.uint8)
+        if offset is None:
+            offset = (self.h + 1) if order == 1 else 0
+        n = lib().ox_encode_offset(self._h, _ptr(img), H, W, offset, ph, pw, _ptr(out), cap)
+        if n < 0:
+            raise OracleError(n, "encode")
+        return out[:n].tobytes()
+
+    def decode(self, data: bytes, H: int, W: int, order: int = 0, ph: int = 0, pw: int = 0,
+               offset: int | None = None) -> np.ndarray:
+        buf = np.frombuffer(data, dtype=np.uint8).copy()
+        img = np.zeros((H, W, 3), dtype=np.uint8)
+        if offset is None:
+            offset = (self.h + 1) if order == 1 else 0
+        rc = lib().ox_decode_offset(self._h, _ptr(buf), buf.size, H, W, offset, ph, pw, _ptr(img))
+        if rc:
+            raise OracleError(rc, "decode")
+        return img
+
+
+def rans_encode(start, freq) -> bytes:
+    s = np.ascontiguousarray(start, dtype=np.uint32)
+    f = np.ascontiguousarray(freq, dtype=np.uint32)
+    cap = 8 + 2 * s.size + 16
+    out = np.zeros(cap, dtype=np.uint8)
+    n = lib().ox_rans_encode(_ptr(s), _ptr(f), s.size, _ptr(out), cap)
+    if n < 0:
+        raise OracleError(n, "rans_encode")
+    return out[:n].tobytes()
+
+
+def rans_decode(cdfs: np.ndarray, data: bytes):
+    """cdfs: (N, 257) int32 rows; returns (symbols, ok)."""
+    c = np.ascontiguousarray(cdfs, dtype=np.int32)
+    N = c.shape[0]
+    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    sym = np.zeros(N, dtype=np.int32)
+    rc = lib().ox_rans_decode(_ptr(c), N, _ptr(buf), buf.size, _ptr(sym))
+    return sym, rc == 0
+
+
+def symbol_order(H: int, W: int, offset: int) -> np.ndarray:
+    """Decode order of a lane as an (N, 3) array of (i, j, channel)."""
+    seq = np.zeros((3 * H * W, 3), dtype=np.int32)
+    n = lib().ox_symbol_order(H, W, offset, _ptr(seq))
+    return seq[:n]
+
+
+def tap_live(h: int, dy: int, dx: int) -> bool:
+    return bool(lib().ox_tap_live(h, dy, dx))
+
+
+def steps(H: int, W: int, h: int) -> int:
+    return int(lib().ox_steps(H, W, h))
+
+
+def log_bin(k: int, mu: float, invs: float) -> float:
+    return float(lib().ox_log_bin(k, mu, invs))
