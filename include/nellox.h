@@ -1,0 +1,156 @@
+/*
+ * nellox.h -- C ABI of nellox, an MI355X (gfx950) implementation of parallel
+ * neural local lossless compression (Zhang, Townsend, Kang, Barber,
+ * "Parallel Neural Local Lossless Compression", arXiv 2201.05213).
+ *
+ * What the library computes
+ *   An image x in {0..255}^(H x W x 3) is coded into a byte string and back
+ *   (Sec. 2: a stream coder driven by an autoregressive model). The model is
+ *   the local autoregressive model of Eq. (3) with horizon h: pixel (i,j)
+ *   depends on rows i-h..i-1 (columns j-h..j+h) and on row i (columns
+ *   j-h..j-1), zero padded, realised as a causal first convolution followed
+ *   by 1x1 layers (Sec. 2.1). Its head is a 10-component discretised logistic
+ *   mixture over each channel, R then G then B, each channel's weights
+ *   conditioned on the earlier channels and its mean shifted linearly by them.
+ *   Probabilities are quantised to 16-bit CDFs
+ *       cdf_k = k + floor(clamp(F(B_k), 0, 1) * 65280),  B_k = (2k - 256)/255,
+ *   so every symbol has frequency >= 1 and the total is 2^16, and coded with
+ *   byte-renormalising rANS (32-bit state, L = 2^23, start state 1).
+ *   Decoding order (nellox_opts.order):
+ *     0 raster: one pixel after the other (the sequential decoder of Sec. 2);
+ *     1 wavefront: pixel (i,j) at step t = j + (h+1) i, all pixels of a step
+ *       in parallel (Sec. 3, Fig. 3, Algorithm 1): W + (h+1)(H-1) steps.
+ *   Patches: the image is cut into patch_h x patch_w tiles anchored at (0,0),
+ *   row-major, ragged at the right/bottom edges; each tile is coded as an
+ *   independent image with its own rANS stream ("lane"), and all lanes of all
+ *   images of a call are decoded concurrently. patch 0 = the whole image.
+ *
+ * Conventions
+ *   - Device pointers are HIP device memory on the current device; the
+ *     caller owns every buffer and the stream (a hipStream_t passed as void*;
+ *     NULL = the default stream). Calls enqueue work on that stream and
+ *     return without waiting for it, except where noted.
+ *   - The library owns only the model handle (device weights and a small
+ *     pinned staging buffer for per-call plans).
+ *   - A non-OK return means nothing was enqueued; nellox_last_error() gives
+ *     a thread-local message. Data errors found by the GPU (a corrupt
+ *     container, a model hash mismatch) are reported per image in the
+ *     device status array of nellox_decode.
+ *   - Images are uint8, H x W x 3, row-major, channel-interleaved (HWC),
+ *     1 <= H, W <= 65535.
+ */
+#ifndef NELLOX_H
+#define NELLOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nellox_model nellox_model; /* opaque, immutable after create */
+
+typedef enum {
+  NELLOX_OK = 0,
+  NELLOX_E_ARG = 1,            /* bad argument (null pointer, size out of range) */
+  NELLOX_E_BLOB = 2,           /* weight blob malformed or its hash is wrong */
+  NELLOX_E_CAPACITY = 3,       /* output or workspace buffer too small */
+  NELLOX_E_CORRUPT = 4,        /* (device status) container damaged */
+  NELLOX_E_MODEL_MISMATCH = 5, /* (device status) container made by another model */
+  NELLOX_E_HIP = 6,            /* a HIP runtime call failed */
+  NELLOX_E_UNSUPPORTED = 7     /* model dimensions this build has no kernel for */
+} nellox_status;
+
+typedef struct {
+  int32_t order;   /* 0 raster, 1 wavefront */
+  int32_t patch_h; /* patch rows; <= 0 or >= H: whole image */
+  int32_t patch_w; /* patch columns; <= 0 or >= W: whole image */
+  int32_t reserved;
+} nellox_opts;
+
+typedef struct {
+  uint8_t* px; /* device pointer to H*W*3 bytes */
+  int32_t H, W;
+} nellox_image;
+
+/* Weight blob (little endian): "NLXW", u32 version = 1, u32 h, u32 C,
+ * u32 n_blocks, u32 n_mix = 10, u32 flags = 1, then FP32 tensors
+ *   conv_w[C][3][2h+1][2h+1] (only the causal taps are read), conv_b[C],
+ *   per block: w1[C][C], b1[C], w2[C][C], b2[C],
+ *   head_w[100][C], head_b[100],
+ * then u64 FNV-1a of all preceding bytes. Head outputs: [0,10) mixture
+ * logits, [10+10c, 20+10c) means of channel c, [40+10c, 50+10c) log-scales of
+ * channel c (floored at -7), [70,80) [80,90) [90,100) pre-tanh coefficients of
+ * G|R, B|R, B|G. Each block computes a += W2 elu(W1 elu(a) + b1) + b2; the head
+ * reads elu(a). Inputs are normalised as v/127.5 - 1.
+ * `blob` is host memory; it is copied. Supported: h in {1,2,3} with
+ * C <= 32 (h = 1) or C <= 64 (h = 2, 3), within the per-CU LDS budget. */
+nellox_status nellox_model_create(const void* blob, size_t blob_bytes, nellox_model** out);
+void nellox_model_destroy(nellox_model* m);
+/* dims = {h, C, n_blocks, n_mix}; hash = the blob's FNV-1a trailer */
+nellox_status nellox_model_info(const nellox_model* m, int32_t dims[4], uint64_t* hash);
+
+/* Upper bound on the container bytes of one H x W image. */
+size_t nellox_encode_bound(int32_t H, int32_t W, const nellox_opts* opts);
+
+/* Device workspace bytes that encode, decode, nll and the debug calls need
+ * for this batch (the maximum over them). */
+size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* opts);
+
+/* Encode n images (Sec. 2 stream coding; every pixel's CDF is computed in one
+ * full-image pass, then each lane is rANS-coded in reverse decode order).
+ * out: device buffer of out_cap bytes, at least the sum of
+ * nellox_encode_bound over the images; image k's container is written at
+ * out + out_offsets[k], out_offsets has n+1 device entries (the last = total).
+ * ws: device workspace of ws_bytes >= nellox_workspace_bytes. */
+nellox_status nellox_encode(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* opts,
+                            uint8_t* out, size_t out_cap, uint64_t* out_offsets, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Read H, W, order and patch shape from a container header in host memory. */
+nellox_status nellox_peek(const uint8_t* container, size_t len, int32_t* H, int32_t* W, nellox_opts* opts);
+
+/* Decode n containers (device buffer `in`, image k at in[in_offsets[k] ..
+ * in_offsets[k+1]), in_offsets on the device) into the preallocated images
+ * out[k] (H, W from nellox_peek). opts must match the containers (order and
+ * patch shape). status: n device int32, set to NELLOX_OK or a data error per
+ * image. Wavefront order runs Algorithm 1 of the paper per lane, with all
+ * lanes of the batch in one persistent launch. */
+nellox_status nellox_decode(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
+                            const nellox_opts* opts, const nellox_image* out, int32_t* status, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* As nellox_decode, and also writes the (start | freq << 16) the decoder used
+ * for every pixel and channel to sym_dump (device, sum of H*W*3 uint32, images
+ * in order) -- for bitwise comparison with nellox_debug_symbols. */
+nellox_status nellox_decode_trace(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
+                                  const nellox_opts* opts, const nellox_image* out, int32_t* status,
+                                  uint32_t* sym_dump, void* ws, size_t ws_bytes, void* stream);
+
+/* Continuous code length -log2 p(x) of each image under the model (Eq. 2's
+ * objective): bits_per_px (nullable, device, sum of H*W floats) and
+ * bits_total (device, n doubles). opts.patch_* selects the patch grid. */
+nellox_status nellox_nll(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* opts,
+                         float* bits_per_px, double* bits_total, void* ws, size_t ws_bytes, void* stream);
+
+/* The encoder's symbols: (start | freq << 16) per pixel and channel (device,
+ * sum of H*W*3 uint32) and its quantised ideal code length per image
+ * (device, n doubles, nullable). */
+nellox_status nellox_debug_symbols(const nellox_model* m, int32_t n, const nellox_image* imgs,
+                                   const nellox_opts* opts, uint32_t* sym, double* ideal_bits, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* Full quantised CDF rows of one image as the encoder computes them:
+ * cdf (device) [H*W][3][257] int32, channel rows conditioned on the image's
+ * own earlier channels. */
+nellox_status nellox_debug_cdf(const nellox_model* m, const nellox_image* img, const nellox_opts* opts,
+                               int32_t* cdf, void* ws, size_t ws_bytes, void* stream);
+
+const char* nellox_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NELLOX_H */

@@ -1,0 +1,329 @@
+// nx_device.hpp -- the fused per-pixel routine shared by every kernel that
+// evaluates the model: causal gather, masked first layer, 1x1 residual blocks,
+// head, mixture parameters, quantised CDF point evaluation, channel posterior.
+//
+// Determinism contract: the encoder's full-image pass and the decoder's
+// wavefront/raster passes call exactly these functions, so their CDFs agree
+// bit for bit. Everything is FP32 with a fixed operation order: the library is
+// built with -ffp-contract=off, FMAs are written out where wanted, sums over
+// mixture components use one fixed tree, and the exp/log/sigmoid used here are
+// this file's own (hardware exp2/log2/rcp plus explicit range reduction).
+//
+// Wave layout ("transposed tile"): a wave evaluates 16 pixels at once. Lane
+// l = p + 16 g holds pixel p (0..15) and lane group g (0..3). The network runs
+// on v_mfma_f32_16x16x4f32 with A = weights (16 output rows x 4 inputs) and
+// B = activations (4 inputs x 16 pixels), so the result D (16 output rows x
+// 16 pixels) leaves row 16 mt + 4 g + v of pixel p in VGPR v of lane (p, g).
+// Read as a B operand, VGPR q of tile ct supplies input channel 16 ct + 4 g + q
+// of pixel p: layer outputs feed the next layer without any data movement.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nx_layout.hpp"
+
+namespace nx {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+#define NXD __device__ __forceinline__
+
+// ------------------------------------------------------------------ math
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.693147180559945309f;
+// two-part ln 2 for the additive range reduction of exp (Cody & Waite): the
+// high part has 16 trailing zero bits so n * hi is exact for |n| < 2^8
+constexpr float kLn2Hi = 0.693145751953125f;
+constexpr float kLn2Lo = 1.42860682030941723e-06f;
+
+// exp(x): x = n ln2 + r, |r| <= ln2/2, exp(r) from the hardware exp2 of
+// r log2(e) (argument in [-1/2, 1/2]), scaled by 2^n.
+NXD float xexp(float x) {
+  x = fminf(fmaxf(x, -200.0f), 200.0f);
+  float n = __builtin_rintf(x * kLog2e);
+  float r = __builtin_fmaf(-n, kLn2Hi, x);
+  r = __builtin_fmaf(-n, kLn2Lo, r);
+  float e = __builtin_amdgcn_exp2f(r * kLog2e);
+  return __builtin_ldexpf(e, (int)n);
+}
+
+// natural log of x > 0 from the hardware log2
+NXD float xlog(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+
+// log(1 + u) for u >= 0, with the rounding of 1 + u compensated
+// (log(v) * u / (v - 1), v = fl(1 + u); Goldberg 1991, Theorem 4)
+NXD float xlog1p(float u) {
+  float v = 1.0f + u;
+  float d = v - 1.0f;
+  return d == 0.0f ? u : xlog(v) * (u / d);
+}
+
+// exp(x) - 1: Taylor polynomial through x^9/9! for |x| < ln2/2, else exp - 1
+NXD float xexpm1(float x) {
+  if (__builtin_fabsf(x) < 0.34657359f) {
+    float q = 2.75573192e-06f;             // 1/9!
+    q = __builtin_fmaf(q, x, 2.48015873e-05f);  // 1/8!
+    q = __builtin_fmaf(q, x, 1.98412698e-04f);  // 1/7!
+    q = __builtin_fmaf(q, x, 1.38888889e-03f);  // 1/6!
+    q = __builtin_fmaf(q, x, 8.33333333e-03f);  // 1/5!
+    q = __builtin_fmaf(q, x, 4.16666667e-02f);  // 1/4!
+    q = __builtin_fmaf(q, x, 1.66666667e-01f);  // 1/3!
+    q = __builtin_fmaf(q, x, 0.5f);             // 1/2!
+    return __builtin_fmaf(x * x, q, x);
+  }
+  return xexp(x) - 1.0f;
+}
+
+NXD float xtanh(float x) {
+  float e = xexpm1(-2.0f * __builtin_fabsf(x));  // in (-1, 0]
+  float t = -e / (e + 2.0f);
+  return __builtin_copysignf(t, x);
+}
+
+NXD float xelu(float x) { return x > 0.0f ? x : xexpm1(x); }
+
+// logistic sigmoid: monotone non-decreasing in z because the hardware exp2
+// and reciprocal are monotone (checked exhaustively over all FP32 inputs)
+NXD float xsigmoid(float z) {
+  float e = __builtin_amdgcn_exp2f(-z * kLog2e);
+  return __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// log sigmoid(z) = min(z, 0) - log1p(exp(-|z|))
+NXD float xlogsigmoid(float z) {
+  return fminf(z, 0.0f) - xlog1p(xexp(-__builtin_fabsf(z)));
+}
+
+// normalised pixel value v/127.5 - 1 (exact numerator, rounded reciprocal)
+NXD float normalise(int v) { return (float)(2 * v - 255) * (1.0f / 255.0f); }
+
+// lower edge of bin k (1..255): (2k - 256)/255
+NXD float bin_edge(int k) { return (float)(2 * k - 256) * (1.0f / 255.0f); }
+
+// ------------------------------------------------------------------ lane group reductions
+// A pixel's mixture is spread over its four lanes p + 16 g; these combine one
+// value per lane group with a fixed tree (v0 + v1) + (v2 + v3). IEEE addition
+// is commutative, so every lane of the pixel obtains the same bits.
+NXD float grp_sum(float v) {
+  v = v + __shfl_xor(v, 16);
+  v = v + __shfl_xor(v, 32);
+  return v;
+}
+NXD float grp_max(float v) {
+  v = fmaxf(v, __shfl_xor(v, 16));
+  v = fmaxf(v, __shfl_xor(v, 32));
+  return v;
+}
+
+// ------------------------------------------------------------------ gather
+// Causal context of pixel (i, j) of a lane (a rect of Hl x Wl pixels at (y0, x0)
+// of an image with row length W): input index k = 3 tap + ch over the taps in
+// raster order (h rows of 2h+1, then h to the left in row i); lane group g
+// gathers k = 4 kc + g for K-chunk kc. Outside the lane reads as 0.
+template <int H_>
+NXD void gather(float (&ctx)[conv_chunks(H_)], const uint8_t* __restrict__ img, int W, int y0, int x0, int Hl,
+                int Wl, int i, int j, bool active, int g) {
+  constexpr int K = 2 * H_ + 1;
+#pragma unroll
+  for (int kc = 0; kc < conv_chunks(H_); ++kc) {
+    const int k = 4 * kc + g;
+    const int tap = k / 3, ch = k - 3 * (k / 3);
+    const int dy = tap < H_ * K ? tap / K : H_;
+    const int dx = tap < H_ * K ? tap - K * (tap / K) : tap - H_ * K;
+    const int y = i - H_ + dy, x = j - H_ + dx;
+    const bool ok = active && y >= 0 && y < Hl && x >= 0 && x < Wl;
+    float v = 0.0f;
+    if (ok) v = normalise(img[((int64_t)(y0 + y) * W + (x0 + x)) * 3 + ch]);
+    ctx[kc] = v;
+  }
+}
+
+// ------------------------------------------------------------------ network
+// One 1x1 layer: out[mt] (pre-initialised with the bias) += W in, K-chunks in
+// the order (ct, q) = (0,0), (0,1), ..., (C/16-1, 3).
+template <int MT_OUT, int CT_IN>
+NXD void layer_mm(const float* __restrict__ w, const f4 (&in)[CT_IN], f4 (&out)[MT_OUT], int lane) {
+#pragma unroll
+  for (int ct = 0; ct < CT_IN; ++ct) {
+    f4 wv[MT_OUT];
+#pragma unroll
+    for (int mt = 0; mt < MT_OUT; ++mt) wv[mt] = *(const f4*)(w + (((int64_t)mt * CT_IN + ct) * 64 + lane) * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int mt = 0; mt < MT_OUT; ++mt)
+        out[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[mt][q], in[ct][q], out[mt], 0, 0, 0);
+  }
+}
+
+template <int N>
+NXD void bias_init(f4 (&a)[N], const float* __restrict__ b, int g) {
+#pragma unroll
+  for (int mt = 0; mt < N; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[mt][v] = b[16 * mt + 4 * g + v];
+}
+
+// Network of a 16-pixel tile: head[8] receives the 128 (permuted) head rows.
+// w points at the weight image (LDS). ctx is this lane's conv B operand.
+template <int H_, int C_>
+NXD void net_forward(const float* __restrict__ w, int nb, const float (&ctx)[conv_chunks(H_)], f4 (&head)[HEAD_TILES],
+                     int lane) {
+  constexpr int MT = C_ / 16;
+  constexpr int KC = conv_chunks(H_), KQ = conv_quads(H_);
+  const WeightLayout L = weight_layout(H_, C_, 0);
+  const int g = lane >> 4;
+  const int64_t layer_stride = (int64_t)MT * MT * 256;
+  const float* bias_conv = w + L.head + (int64_t)HEAD_TILES * MT * 256 + 2 * (int64_t)nb * layer_stride;
+  const float* bias_blk = bias_conv + C_;
+  const float* bias_head = bias_blk + 2 * (int64_t)nb * C_;
+  const float* w_head = w + L.layer0 + 2 * (int64_t)nb * layer_stride;
+
+  f4 a[MT];
+  bias_init(a, bias_conv, g);
+#pragma unroll
+  for (int kq = 0; kq < KQ; ++kq) {
+    f4 wv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) wv[mt] = *(const f4*)(w + (((int64_t)mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (4 * kq + q < KC) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          a[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[mt][q], ctx[4 * kq + q], a[mt], 0, 0, 0);
+      }
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    f4 u[MT], z[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u[mt][v] = xelu(a[mt][v]);
+    bias_init(z, bias_blk + (int64_t)(2 * b) * C_, g);
+    layer_mm<MT, MT>(w + L.layer0 + (int64_t)(2 * b) * layer_stride, u, z, lane);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u[mt][v] = xelu(z[mt][v]);
+    bias_init(z, bias_blk + (int64_t)(2 * b + 1) * C_, g);
+    layer_mm<MT, MT>(w + L.layer0 + (int64_t)(2 * b + 1) * layer_stride, u, z, lane);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a[mt] = a[mt] + z[mt];
+  }
+  f4 u[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[mt][v] = xelu(a[mt][v]);
+  bias_init(head, bias_head, g);
+  layer_mm<HEAD_TILES, MT>(w_head, u, head, lane);
+}
+
+// ------------------------------------------------------------------ mixture
+// Head slot s = 4 mt + v of lane group g holds parameter s % 10 of component
+// m = g + 4 (s / 10) (s < 30, m < 10): 0 logit, 1..3 means R,G,B,
+// 4..6 raw log-scales R,G,B, 7..9 pre-tanh coefficients G|R, B|R, B|G.
+// Lane groups 0,1 own three components, groups 2,3 own two (slot 2 unused).
+struct Mix {
+  float logw[3];       // current (posterior) log weights
+  float mu[3][3];      // [channel][slot] base means
+  float invs[3][3];    // [channel][slot] inverse scales
+  float co[3][3];      // [coef][slot] tanh'd coefficients alpha, beta, gamma
+};
+
+NXD float head_slot(const f4 (&hd)[HEAD_TILES], int s) { return hd[s >> 2][s & 3]; }
+
+// log-sum-exp over the ten components of one pixel (own slots, fixed tree)
+NXD float lse10(const float (&t)[3], bool has2) {
+  float m = fmaxf(t[0], t[1]);
+  if (has2) m = fmaxf(m, t[2]);
+  m = grp_max(m);
+  float s = xexp(t[0] - m) + xexp(t[1] - m);
+  s = s + (has2 ? xexp(t[2] - m) : 0.0f);
+  s = grp_sum(s);
+  return m + xlog(s);
+}
+
+NXD void mix_prep(const f4 (&hd)[HEAD_TILES], Mix& M, bool has2) {
+  float lam[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) lam[j] = head_slot(hd, 10 * j);
+  if (!has2) lam[2] = -INFINITY;
+  const float lse = lse10(lam, has2);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    M.logw[j] = lam[j] - lse;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      M.mu[c][j] = head_slot(hd, 10 * j + 1 + c);
+      M.invs[c][j] = xexp(-fmaxf(head_slot(hd, 10 * j + 4 + c), -7.0f));
+      M.co[c][j] = xtanh(head_slot(hd, 10 * j + 7 + c));
+    }
+  }
+}
+
+// Mixture of channel c given the normalised values of the earlier channels:
+// weights, shifted means, inverse scales of this lane's slots.
+NXD void chan_params(const Mix& M, int c, float xr, float xg, float (&w)[3], float (&mu)[3], float (&is)[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    w[j] = xexp(M.logw[j]);
+    is[j] = M.invs[c][j];
+    float m = M.mu[c][j];
+    if (c == 1) m = m + M.co[0][j] * xr;
+    if (c == 2) {
+      const float t1 = M.co[1][j] * xr;
+      const float t2 = M.co[2][j] * xg;
+      m = (m + t1) + t2;
+    }
+    mu[j] = m;
+  }
+}
+
+// Mixture CDF at bin edge k (1..255) as F = sum_m w_m sigmoid((B_k - mu_m) s_m),
+// the sum taken per lane group over its slots in order, then across groups.
+// Every lane of a pixel must call this with the same k (lane-group shuffles).
+NXD float cdf_eval(int k, const float (&w)[3], const float (&mu)[3], const float (&is)[3]) {
+  const float b = bin_edge(k);
+  float t[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) t[j] = w[j] * xsigmoid((b - mu[j]) * is[j]);
+  const float s = (t[0] + t[1]) + t[2];
+  return grp_sum(s);
+}
+
+// Quantised CDF value: k + floor(clamp(F, 0, 1) * (2^16 - 256)). Monotone in
+// k whenever F is, with a step of at least 1 between consecutive symbols.
+NXD uint32_t cdf_quant(int k, float F) {
+  const float c = fminf(fmaxf(F, 0.0f), 1.0f);
+  return (uint32_t)k + (uint32_t)(c * 65280.0f);
+}
+
+// log probability of bin x under this lane's slots (Q: stable difference of
+// logistic CDFs: log sig(z_hi) + log sig(-z_lo) + log(1 - exp(-(z_hi - z_lo))),
+// with z_hi - z_lo = (2/255) s exactly in real arithmetic).
+NXD float log_bin(int x, float mu, float is) {
+  if (x <= 0) return xlogsigmoid((bin_edge(1) - mu) * is);
+  if (x >= 255) return xlogsigmoid(-((bin_edge(255) - mu) * is));
+  const float zlo = (bin_edge(x) - mu) * is;
+  const float zhi = (bin_edge(x + 1) - mu) * is;
+  const float d = is * (2.0f / 255.0f);
+  return (xlogsigmoid(zhi) + xlogsigmoid(-zlo)) + xlog(-xexpm1(-d));
+}
+
+// Condition the weights on the coded value x of channel c (posterior for the
+// next channel); returns the channel's natural-log probability.
+NXD float posterior(Mix& M, int x, const float (&mu)[3], const float (&is)[3], bool has2) {
+  float t[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) t[j] = M.logw[j] + log_bin(x, mu[j], is[j]);
+  if (!has2) t[2] = -INFINITY;
+  const float lse = lse10(t, has2);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) M.logw[j] = t[j] - lse;
+  return lse;
+}
+
+}  // namespace nx

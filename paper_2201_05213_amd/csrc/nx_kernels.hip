@@ -1,0 +1,579 @@
+// nx_kernels.hip -- HIP kernels for gfx950 (MI355X):
+//   k_pass      full-image pass: every pixel's quantised CDF at its own value
+//               (encoder symbols), or its continuous code length (NLL), or a
+//               full CDF row (debug), 16 pixels per wave on MFMA
+//   k_rans_enc  one thread per lane: rANS-encodes the lane's symbols in
+//               reverse decode order into a private slot
+//   k_lane_scan / k_img_scan / k_pack   container assembly
+//   k_decode    persistent decoder: waves pop lanes from a queue and decode
+//               them step by step (wavefront) or pixel by pixel (raster)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nx_device.hpp"
+#include "nx_kernels.hpp"
+
+namespace nx {
+
+constexpr int NWAVES = 8;  // waves per persistent workgroup (all share the LDS weights)
+
+NXD int find_img(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = by_lane ? d[mid].lane_base : d[mid].tile_base;
+    if (b <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+NXD uint32_t rd_u32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+NXD int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The weight image is never written after it is staged in LDS, so the
+// compiler would hoist every weight read out of the persistent loops and try
+// to keep the whole network in registers. An offset it cannot see through
+// (always 0) keeps the reads next to their MFMAs.
+NXD const float* lds_weights(const float* w) {
+  int zero = 0;
+  asm volatile("" : "+s"(zero));
+  return w + zero;
+}
+NXD uint32_t uniform_u(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// rows active at wavefront step t of an Hl x Wl lane, step offset o = h + 1
+NXD void step_rows(int t, int Hl, int Wl, int o, int& ilo, int& ihi) {
+  const int a = t - (Wl - 1);
+  ilo = a <= 0 ? 0 : (a + o - 1) / o;
+  ihi = min(Hl - 1, t / o);
+}
+
+template <int NT>
+NXD void load_weights(float* lds, const float* __restrict__ w, int64_t nfloats) {
+  const int64_t n4 = nfloats >> 2;
+  for (int64_t i = threadIdx.x; i < n4; i += NT) ((float4*)lds)[i] = ((const float4*)w)[i];
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ full-image pass
+template <int H_, int C_>
+__global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
+  extern __shared__ float4 smem_f4[];
+  float* w = (float*)smem_f4;
+  load_weights<NWAVES * 64>(w, A.w, A.wfloats);
+  const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
+  const bool has2 = g < 2;
+  const int64_t gw = (int64_t)blockIdx.x * NWAVES + (threadIdx.x >> 6);
+  const int64_t nwv = (int64_t)gridDim.x * NWAVES;
+  for (int64_t t = gw; t < A.n_tiles; t += nwv) {
+    const int n = find_img(A.desc, A.n_img, t, false);
+    const ImgDesc D = A.desc[n];
+    const int64_t tt = t - D.tile_base;
+    const int y = (int)(tt / D.ntx);
+    const int xraw = (int)(tt - (int64_t)y * D.ntx) * 16 + p;
+    const bool active = xraw < D.W;
+    const int x = active ? xraw : D.W - 1;
+    const int ly = y / D.ph, lx = x / D.pw;
+    const int y0 = ly * D.ph, x0 = lx * D.pw;
+    const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
+    float ctx[conv_chunks(H_)];
+    gather<H_>(ctx, D.px, D.W, y0, x0, Hl, Wl, y - y0, x - x0, active, g);
+    f4 head[HEAD_TILES];
+    net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
+    Mix M;
+    mix_prep(head, M, has2);
+    const int64_t pix = (int64_t)y * D.W + x;
+    int xv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv[c] = D.px[pix * 3 + c];
+    const float xr = normalise(xv[0]), xg = normalise(xv[1]);
+    float bits = 0.0f;
+    const int64_t gpix = D.px_base + pix;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float wc[3], mu[3], is[3];
+      chan_params(M, c, xr, xg, wc, mu, is);
+      if (A.mode == 0) {
+        const float Flo = cdf_eval(max(xv[c], 1), wc, mu, is);
+        const float Fhi = cdf_eval(min(xv[c] + 1, 255), wc, mu, is);
+        const uint32_t lo = xv[c] == 0 ? 0u : cdf_quant(xv[c], Flo);
+        const uint32_t hi = xv[c] == 255 ? CDF_TOTAL : cdf_quant(xv[c] + 1, Fhi);
+        if (active && g == 0) A.sym[gpix * 3 + c] = lo | ((hi - lo) << 16);
+        bits += (float)CDF_BITS - __builtin_amdgcn_logf((float)(hi - lo));
+        if (c < 2) posterior(M, xv[c], mu, is, has2);
+      } else if (A.mode == 1) {
+        const float lp = posterior(M, xv[c], mu, is, has2);
+        bits += -lp * kLog2e;
+      } else {
+        for (int k = 1; k < 256; ++k) {
+          const uint32_t v = cdf_quant(k, cdf_eval(k, wc, mu, is));
+          if (active && g == 0) A.cdf[(gpix * 3 + c) * 257 + k] = (int32_t)v;
+        }
+        if (active && g == 0) {
+          A.cdf[(gpix * 3 + c) * 257] = 0;
+          A.cdf[(gpix * 3 + c) * 257 + 256] = (int32_t)CDF_TOTAL;
+        }
+        if (c < 2) posterior(M, xv[c], mu, is, has2);
+      }
+    }
+    if (A.bits && active && g == 0) A.bits[gpix] = bits;
+  }
+}
+
+// ------------------------------------------------------------------ rANS encoder
+// Symbols of a lane in decode order:
+//   wavefront: steps t ascending; within a step the active rows are cut into
+//   groups of 16 consecutive rows; per group channels R, G, B; per channel
+//   rows ascending.
+//   raster: rows, columns, channels.
+// The encoder walks this order backwards.
+struct RevOrder {
+  int Hl, Wl, o, raster;
+  int t, ilo, ihi, ts, te, c, i, j;
+  bool done;
+
+  // enter step t, or the closest earlier non-empty one: a lane narrower than
+  // h + 1 columns has steps without any pixel (step 0 is never empty)
+  NXD void set_step() {
+    for (;;) {
+      step_rows(t, Hl, Wl, o, ilo, ihi);
+      if (ilo <= ihi) break;
+      if (--t < 0) { done = true; return; }
+    }
+    ts = ilo + ((ihi - ilo) / 16) * 16;
+    te = min(ts + 15, ihi);
+    c = 2;
+    i = te;
+  }
+  NXD void init(int Hl_, int Wl_, int o_, int raster_) {
+    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; done = false;
+    if (raster) { i = Hl - 1; j = Wl - 1; c = 2; }
+    else { t = Wl + o * (Hl - 1) - 1; set_step(); }
+  }
+  // current symbol: row i, column col(), channel c
+  NXD int col() const { return raster ? j : t - o * i; }
+  NXD void advance() {
+    if (raster) {
+      if (--c >= 0) return;
+      c = 2;
+      if (--j >= 0) return;
+      j = Wl - 1;
+      if (--i >= 0) return;
+      done = true;
+      return;
+    }
+    if (--i >= ts) return;
+    if (--c >= 0) { i = te; return; }
+    ts -= 16;
+    if (ts >= ilo) { te = ts + 15; c = 2; i = te; return; }
+    if (--t < 0) { done = true; return; }
+    set_step();
+  }
+};
+
+__global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
+  const int64_t L = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (L >= A.n_lanes) return;
+  const int n = find_img(A.desc, A.n_img, L, true);
+  const ImgDesc D = A.desc[n];
+  const int q = (int)(L - D.lane_base);
+  const int ly = q / D.nlx, lx = q - ly * D.nlx;
+  const int y0 = ly * D.ph, x0 = lx * D.pw;
+  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
+  const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
+  const int64_t slot_end = D.slot_base + 6 * lane_px_off + 8 * (int64_t)q + lane_slot_bytes((int64_t)Hl * Wl);
+  uint8_t* out = A.slots + slot_end;
+  const uint32_t* sym = A.sym + D.px_base * 3;
+  RevOrder it;
+  it.init(Hl, Wl, A.h + 1, A.order == 0);
+  uint32_t x = RANS_X0;
+  constexpr int B = 16;  // symbols fetched per batch (independent loads in flight)
+  while (!it.done) {
+    uint32_t v[B];
+    int nv = 0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      if (!it.done) {
+        const int64_t idx = ((int64_t)(y0 + it.i) * D.W + (x0 + it.col())) * 3 + it.c;
+        v[k] = sym[idx];
+        ++nv;
+        it.advance();
+      }
+    }
+    for (int k = 0; k < nv; ++k) {
+      const uint32_t s = v[k] & 0xffffu, f = v[k] >> 16;
+      const uint32_t xmax = ((RANS_L >> CDF_BITS) << 8) * f;
+      while (x >= xmax) {
+        *--out = (uint8_t)(x & 255u);
+        x >>= 8;
+      }
+      x = ((x / f) << CDF_BITS) + (x % f) + s;
+    }
+  }
+  out -= 4;
+  out[0] = (uint8_t)x;
+  out[1] = (uint8_t)(x >> 8);
+  out[2] = (uint8_t)(x >> 16);
+  out[3] = (uint8_t)(x >> 24);
+  A.lane_len[L] = (uint32_t)((A.slots + slot_end) - out);
+}
+
+// ------------------------------------------------------------------ container assembly
+// per image: lane_end (inclusive prefix of lane lengths), container bytes
+__global__ void __launch_bounds__(256) k_lane_scan(PackArgs A) {
+  __shared__ uint32_t part[256];
+  __shared__ uint32_t carry;
+  const int n = blockIdx.x;
+  const ImgDesc D = A.desc[n];
+  const int nl = D.nlx * D.nly;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nl; b0 += 256) {
+    const int q = b0 + threadIdx.x;
+    const uint32_t v = q < nl ? A.lane_len[D.lane_base + q] : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (q < nl) A.lane_end[D.lane_base + q] = carry + part[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 255) carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.img_bytes[n] = (uint64_t)HDR_BYTES + 4ull * nl + carry;
+}
+
+__global__ void k_img_scan(PackArgs A) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t acc = 0;
+  for (int n = 0; n < A.n_img; ++n) {
+    A.out_offsets[n] = acc;
+    acc += A.img_bytes[n];
+  }
+  A.out_offsets[A.n_img] = acc;
+  *A.overflow = acc > A.out_cap ? 1 : 0;
+}
+
+// one 64-thread block per lane: payload copy, lane table entry, header
+__global__ void __launch_bounds__(64) k_pack(PackArgs A) {
+  if (*A.overflow) return;
+  const int64_t L = blockIdx.x;
+  const int n = find_img(A.desc, A.n_img, L, true);
+  const ImgDesc D = A.desc[n];
+  const int q = (int)(L - D.lane_base);
+  const int nl = D.nlx * D.nly;
+  const int ly = q / D.nlx, lx = q - ly * D.nlx;
+  const int y0 = ly * D.ph, x0 = lx * D.pw;
+  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
+  (void)x0;
+  const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
+  const int64_t slot_end = D.slot_base + 6 * lane_px_off + 8 * (int64_t)q + lane_slot_bytes((int64_t)Hl * Wl);
+  const uint32_t len = A.lane_len[L];
+  const uint32_t end = A.lane_end[L];
+  uint8_t* C = A.out + A.out_offsets[n];
+  uint8_t* dst = C + HDR_BYTES + 4 * (int64_t)nl + (end - len);
+  const uint8_t* src = A.slots + slot_end - len;
+  for (uint32_t k = threadIdx.x; k < len; k += 64) dst[k] = src[k];
+  if (threadIdx.x < 4) C[HDR_BYTES + 4 * (int64_t)q + threadIdx.x] = (uint8_t)(end >> (8 * threadIdx.x));
+  if (q == 0 && threadIdx.x == 0) {
+    uint8_t h[HDR_BYTES];
+    for (int k = 0; k < HDR_BYTES; ++k) h[k] = 0;
+    h[0] = 'N'; h[1] = 'L'; h[2] = 'X'; h[3] = 'C';
+    h[4] = CONTAINER_VERSION;
+    h[5] = (uint8_t)A.order;
+    h[6] = (uint8_t)A.h;
+    h[7] = CODER_RANS8;
+    for (int k = 0; k < 4; ++k) h[8 + k] = (uint8_t)((uint32_t)D.H >> (8 * k));
+    for (int k = 0; k < 4; ++k) h[12 + k] = (uint8_t)((uint32_t)D.W >> (8 * k));
+    const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
+    h[16] = (uint8_t)ph; h[17] = (uint8_t)(ph >> 8);
+    h[18] = (uint8_t)pw; h[19] = (uint8_t)(pw >> 8);
+    for (int k = 0; k < 8; ++k) h[20 + k] = (uint8_t)(A.model_hash >> (8 * k));
+    for (int k = 0; k < 4; ++k) h[28 + k] = (uint8_t)((uint32_t)nl >> (8 * k));
+    for (int k = 0; k < HDR_BYTES; ++k) C[k] = h[k];
+  }
+}
+
+// ------------------------------------------------------------------ decoder
+// Bytes of the lane payload, staged 256 at a time: lane l of the wave holds
+// bytes base + 4l .. base + 4l + 3; a byte is fetched with a lane read.
+struct ByteStage {
+  const uint8_t* S;
+  int64_t len, base;
+  uint32_t word;
+  NXD void fill(int64_t at, int lane) {
+    base = at;
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t o = at + 4 * lane + b;
+      if (o < len) v |= (uint32_t)S[o] << (8 * b);
+    }
+    word = v;
+  }
+  NXD uint32_t get(int64_t pos, int lane) {
+    if (pos - base >= 256) fill(pos, lane);
+    const int off = (int)(pos - base);
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)word, off >> 2);
+    return (v >> (8 * (off & 3))) & 255u;
+  }
+};
+
+template <int H_, int C_>
+__device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lane) {
+  const int p = lane & 15, g = lane >> 4;
+  const bool has2 = g < 2;
+  const int n = find_img(A.desc, A.n_img, L, true);
+  const ImgDesc D = A.desc[n];
+  const int q = (int)(L - D.lane_base);
+  const int nl = D.nlx * D.nly;
+  const int ly = q / D.nlx, lx = q - ly * D.nlx;
+  const int y0 = ly * D.ph, x0 = lx * D.pw;
+  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
+  const uint8_t* C = A.in + A.in_off[n];
+  const int64_t clen = (int64_t)(A.in_off[n + 1] - A.in_off[n]);
+  const int64_t pay = HDR_BYTES + 4 * (int64_t)nl;
+  // header and lane table checks (every lane reads the same bytes)
+  bool ok = clen >= pay;
+  if (ok) {
+    const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
+    ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION &&
+         C[5] == (uint8_t)A.order && C[6] == (uint8_t)H_ && C[7] == CODER_RANS8 && rd_u32(C + 8) == (uint32_t)D.H &&
+         rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
+         (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
+    if (ok) {
+      const uint64_t hsh = (uint64_t)rd_u32(C + 20) | ((uint64_t)rd_u32(C + 24) << 32);
+      if (hsh != A.model_hash) {
+        if (lane == 0) A.status[n] = ST_MISMATCH;
+        return;
+      }
+    }
+  }
+  uint32_t lend = 0, lstart = 0;
+  if (ok) {
+    lend = rd_u32(C + HDR_BYTES + 4 * (int64_t)q);
+    lstart = q > 0 ? rd_u32(C + HDR_BYTES + 4 * (int64_t)(q - 1)) : 0u;
+    ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+  }
+  if (!ok) {
+    if (lane == 0) A.status[n] = ST_CORRUPT;
+    return;
+  }
+  ByteStage R;
+  R.S = C + pay + lstart;
+  R.len = (int64_t)(lend - lstart);
+  R.fill(0, lane);
+  uint32_t x = R.get(0, lane) | (R.get(1, lane) << 8) | (R.get(2, lane) << 16) | (R.get(3, lane) << 24);
+  int64_t pos = 4;
+  uint8_t* img = D.px;
+  const int o = H_ + 1;
+  const bool raster = A.order == 0;
+  const int64_t ngroups = raster ? (int64_t)Hl * Wl : (int64_t)Wl + (int64_t)o * (Hl - 1);
+  uint32_t* dump = A.sym_dump ? A.sym_dump + D.px_base * 3 : nullptr;
+
+  for (int64_t gi = 0; gi < ngroups; ++gi) {
+    int ilo, ihi;
+    if (raster) {
+      ilo = ihi = (int)(gi / Wl);
+    } else {
+      step_rows((int)gi, Hl, Wl, o, ilo, ihi);
+    }
+    for (int ts = ilo; ts <= ihi; ts += 16) {
+      const int na = min(16, ihi - ts + 1);
+      const int i = ts + p;
+      const bool active = p < na;
+      const int j = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * i;
+      float ctx[conv_chunks(H_)];
+      gather<H_>(ctx, img, D.W, y0, x0, Hl, Wl, i, j, active, g);
+      f4 head[HEAD_TILES];
+      net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
+      Mix M;
+      mix_prep(head, M, has2);
+      int xv[3] = {0, 0, 0};
+      float xr = 0.0f, xg = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float wc[3], mu[3], is[3];
+        chan_params(M, c, xr, xg, wc, mu, is);
+        for (int pp = 0; pp < na; ++pp) {
+          const int src = (g << 4) | pp;
+          float bw[3], bm[3], bs[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            bw[k] = __shfl(wc[k], src);
+            bm[k] = __shfl(mu[k], src);
+            bs[k] = __shfl(is[k], src);
+          }
+          const uint32_t slot = x & 0xffffu;
+          // round 1: pivots k = 16 (p + 1)
+          const int k1 = 16 * (p + 1);
+          const float F1 = cdf_eval(min(k1, 255), bw, bm, bs);
+          const uint32_t c1 = p == 15 ? CDF_TOTAL : cdf_quant(k1, F1);
+          const int b = __popcll(__ballot(c1 <= slot) & 0xffffull);
+          // round 2: k = 16 b + p inside the bucket
+          const int k2 = 16 * b + p;
+          const float F2 = cdf_eval(max(k2, 1), bw, bm, bs);
+          uint32_t c2 = cdf_quant(k2, F2);
+          const uint32_t cb = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)c1, b - 1);
+          if (p == 0) c2 = cb;
+          const int cnt = __popcll(__ballot(c2 <= slot) & 0xffffull) - 1;
+          const int s = 16 * b + cnt;
+          const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
+          uint32_t next;
+          if (cnt < 15) next = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt + 1);
+          else next = b == 15 ? CDF_TOTAL : (uint32_t)__builtin_amdgcn_readlane((int)c1, b);
+          const uint32_t freq = next - start;
+          x = freq * (x >> 16) + slot - start;
+          while (x < RANS_L && pos < R.len) {
+            x = (x << 8) | R.get(pos, lane);
+            ++pos;
+          }
+          if (p == pp) xv[c] = s;
+          if (dump && lane == 0) {
+            const int ii = ts + pp;
+            const int jj = raster ? j : (int)gi - o * ii;
+            dump[((int64_t)(y0 + ii) * D.W + (x0 + jj)) * 3 + c] = start | (freq << 16);
+          }
+        }
+        if (c < 2) posterior(M, xv[c], mu, is, has2);
+        if (c == 0) xr = normalise(xv[0]);
+        if (c == 1) xg = normalise(xv[1]);
+      }
+      if (active && g == 0) {
+        uint8_t* dst = img + ((int64_t)(y0 + i) * D.W + (x0 + j)) * 3;
+        dst[0] = (uint8_t)xv[0];
+        dst[1] = (uint8_t)xv[1];
+        dst[2] = (uint8_t)xv[2];
+      }
+      // make this group's pixels visible to the wave's later gathers
+      __threadfence_block();
+    }
+  }
+  if (!(x == RANS_X0 && pos == R.len) && lane == 0) A.status[n] = ST_CORRUPT;
+}
+
+template <int H_, int C_>
+__global__ void __launch_bounds__(NWAVES * 64) k_decode(DecArgs A) {
+  extern __shared__ float4 smem_f4[];
+  float* w = (float*)smem_f4;
+  load_weights<NWAVES * 64>(w, A.w, A.wfloats);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int L = 0;
+    if (lane == 0) L = atomicAdd(A.counter, 1);
+    L = uniform(L);
+    if ((int64_t)L >= A.n_lanes) break;
+    decode_lane<H_, C_>(A, w, L, lane);
+  }
+}
+
+__global__ void k_decode_prep(int32_t* status, int n_img, int32_t* counter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_img) status[i] = ST_OK;
+  if (i == 0) *counter = 0;
+}
+
+// per image: sum of per-pixel bits in double, fixed order (thread-strided
+// partial sums, then a fixed tree)
+__global__ void __launch_bounds__(256) k_reduce_bits(const ImgDesc* desc, const float* bits, double* out) {
+  __shared__ double part[256];
+  const ImgDesc D = desc[blockIdx.x];
+  const int64_t npx = (int64_t)D.H * D.W;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < npx; k += 256) s += (double)bits[D.px_base + k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+// ------------------------------------------------------------------ host launchers
+bool supported(int h, int C) {
+  return (h == 3 && (C == 16 || C == 32 || C == 64)) || (h == 2 && (C == 16 || C == 32 || C == 64)) ||
+         (h == 1 && (C == 16 || C == 32));
+}
+
+// kernels keep the whole weight image in LDS: allow up to the device limit
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int H_, int C_>
+static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.wfloats * 4;
+  hipError_t e = allow_lds(k_pass<H_, C_>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pass<H_, C_>), dim3(grid), dim3(NWAVES * 64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int H_, int C_>
+static hipError_t decode_t(const DecArgs& a, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.wfloats * 4;
+  hipError_t e = allow_lds(k_decode<H_, C_>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_decode<H_, C_>), dim3(grid), dim3(NWAVES * 64), lds, s, a);
+  return hipGetLastError();
+}
+
+#define NX_DISPATCH(FN, h, C, ...)                          \
+  do {                                                      \
+    if (h == 3 && C == 64) return FN<3, 64>(__VA_ARGS__);   \
+    if (h == 3 && C == 32) return FN<3, 32>(__VA_ARGS__);   \
+    if (h == 3 && C == 16) return FN<3, 16>(__VA_ARGS__);   \
+    if (h == 2 && C == 64) return FN<2, 64>(__VA_ARGS__);   \
+    if (h == 2 && C == 32) return FN<2, 32>(__VA_ARGS__);   \
+    if (h == 2 && C == 16) return FN<2, 16>(__VA_ARGS__);   \
+    if (h == 1 && C == 32) return FN<1, 32>(__VA_ARGS__);   \
+    if (h == 1 && C == 16) return FN<1, 16>(__VA_ARGS__);   \
+    return hipErrorInvalidValue;                            \
+  } while (0)
+
+hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  NX_DISPATCH(pass_t, h, C, a, grid, s);
+}
+
+hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, hipStream_t s) {
+  if (a.n_lanes == 0) return hipSuccess;
+  NX_DISPATCH(decode_t, h, C, a, grid, s);
+}
+
+hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
+  if (a.n_lanes == 0) return hipSuccess;
+  const int grid = (int)((a.n_lanes + 63) / 64);
+  hipLaunchKernelGGL(k_rans_enc, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_lane_scan, dim3(a.n_img), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_img_scan, dim3(1), dim3(64), 0, s, a);
+  if (a.n_lanes > 0) hipLaunchKernelGGL(k_pack, dim3((unsigned)a.n_lanes), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s) {
+  const int grid = (n_img + 255) / 256 > 0 ? (n_img + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_decode_prep, dim3(grid), dim3(256), 0, s, status, n_img, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s) {
+  if (n_img == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_bits, dim3(n_img), dim3(256), 0, s, desc, bits, out);
+  return hipGetLastError();
+}
+
+}  // namespace nx

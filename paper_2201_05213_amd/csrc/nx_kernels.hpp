@@ -1,0 +1,82 @@
+// nx_kernels.hpp -- launch interface between the host runtime (nx_capi.cpp)
+// and the kernels (nx_kernels.hip). Plain structs of device pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nx_layout.hpp"
+
+namespace nx {
+
+// status codes written to the per-image device status array (match nellox.h)
+constexpr int ST_OK = 0;
+constexpr int ST_CORRUPT = 4;
+constexpr int ST_MISMATCH = 5;
+
+struct PassArgs {
+  const float* w;          // device weight image
+  int64_t wfloats;
+  int nb;
+  const ImgDesc* desc;     // device copy of the plan
+  int n_img;
+  int64_t n_tiles;
+  int mode;                // 0 symbols, 1 continuous bits, 2 full CDF rows
+  uint32_t* sym;           // mode 0: (start | freq << 16) per pixel and channel
+  float* bits;             // mode 0: quantised ideal bits per pixel (nullable);
+                           // mode 1: continuous bits per pixel
+  int32_t* cdf;            // mode 2: [pixel][3][257]
+};
+
+struct RansEncArgs {
+  const ImgDesc* desc;
+  int n_img;
+  int64_t n_lanes;
+  int order;               // 0 raster, 1 wavefront
+  int h;
+  const uint32_t* sym;
+  uint8_t* slots;
+  uint32_t* lane_len;
+};
+
+struct PackArgs {
+  const ImgDesc* desc;
+  int n_img;
+  int64_t n_lanes;
+  int order, h;
+  uint64_t model_hash;
+  const uint8_t* slots;
+  const uint32_t* lane_len;
+  uint32_t* lane_end;      // scratch: cumulative payload bytes per lane
+  uint64_t* img_bytes;     // scratch: container bytes per image
+  uint8_t* out;
+  uint64_t* out_offsets;   // n_img + 1
+  uint64_t out_cap;
+  int32_t* overflow;       // set when the containers would exceed out_cap
+};
+
+struct DecArgs {
+  const float* w;
+  int64_t wfloats;
+  int nb;
+  const ImgDesc* desc;     // px = output image
+  int n_img;
+  int64_t n_lanes;
+  int order;
+  uint64_t model_hash;
+  const uint8_t* in;
+  const uint64_t* in_off;  // n_img + 1
+  int32_t* status;         // n_img
+  int32_t* counter;        // work queue head
+  uint32_t* sym_dump;      // nullable: (start | freq << 16) used per pixel/channel
+};
+
+// host launchers (return hipError_t of the launch); h in {1,2,3}, C in {16,32,64}
+bool supported(int h, int C);
+hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s);
+hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, hipStream_t s);
+hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s);
+
+}  // namespace nx
