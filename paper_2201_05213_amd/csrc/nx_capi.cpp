@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nellox.h"
+#include "nellox.h"
 #include "nx_kernels.hpp"
 #include "nx_layout.hpp"
 
@@ -284,7 +284,7 @@ nellox_status nellox_model_create(const void* blob, size_t nbytes, nellox_model*
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (img.size() * 4 > prop.sharedMemPerBlock)
+  if (img.size() * 4 + DECODE_LDS_EXTRA > prop.sharedMemPerBlock)
     return fail(NELLOX_E_UNSUPPORTED, "weights exceed the LDS of one workgroup");
   nellox_model* m = new nellox_model();
   m->h = (int)h; m->C = (int)C; m->Cp = Cp; m->nb = (int)nb;
@@ -441,7 +441,7 @@ static nellox_status decode_impl(const nellox_model* mc, int32_t n, const uint8_
   a.counter = counter;
   a.sym_dump = dump;
   int grid = persistent_grid(m);
-  const int64_t need = (P.n_lanes + 7) / 8;
+  const int64_t need = (P.n_lanes + DECODE_WAVES - 1) / DECODE_WAVES;
   if (need < grid) grid = (int)std::max<int64_t>(need, 1);
   e = launch_decode(m->h, m->Cp, a, grid, s);
   if (e != hipSuccess) return hip_fail(e, "decoder launch");

@@ -80,7 +80,13 @@ NXD float xtanh(float x) {
   return __builtin_copysignf(t, x);
 }
 
-NXD float xelu(float x) { return x > 0.0f ? x : xexpm1(x); }
+// ELU with exp(x) - 1 from the hardware exp2 for x <= 0: the rounding of
+// x log2(e) costs a relative error of at most |x| 2^-24 ln2 in exp(x), i.e.
+// an absolute error below 3e-8 in the activation
+NXD float xelu(float x) {
+  const float e = __builtin_amdgcn_exp2f(fminf(x, 0.0f) * kLog2e) - 1.0f;
+  return x > 0.0f ? x : e;
+}
 
 // logistic sigmoid: monotone non-decreasing in z because the hardware exp2
 // and reciprocal are monotone (checked exhaustively over all FP32 inputs)
@@ -103,15 +109,32 @@ NXD float bin_edge(int k) { return (float)(2 * k - 256) * (1.0f / 255.0f); }
 // ------------------------------------------------------------------ lane group reductions
 // A pixel's mixture is spread over its four lanes p + 16 g; these combine one
 // value per lane group with a fixed tree (v0 + v1) + (v2 + v3). IEEE addition
-// is commutative, so every lane of the pixel obtains the same bits.
+// is commutative, so every lane of the pixel obtains the same bits. The
+// exchanges use the gfx950 row swaps (VALU, no LDS round trip):
+// permlane16_swap exchanges rows 0<->1 and 2<->3, permlane32_swap rows
+// 0,1 <-> 2,3.
+NXD float xor16(float v, int g) {
+  const uint32_t u = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __uint_as_float((g & 1) ? r[0] : r[1]);
+}
+NXD float xor32(float v, int g) {
+  const uint32_t u = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float((g & 2) ? r[0] : r[1]);
+}
+NXD int lane_group() { return (int)(__lane_id() >> 4); }
+
 NXD float grp_sum(float v) {
-  v = v + __shfl_xor(v, 16);
-  v = v + __shfl_xor(v, 32);
+  const int g = lane_group();
+  v = v + xor16(v, g);
+  v = v + xor32(v, g);
   return v;
 }
 NXD float grp_max(float v) {
-  v = fmaxf(v, __shfl_xor(v, 16));
-  v = fmaxf(v, __shfl_xor(v, 32));
+  const int g = lane_group();
+  v = fmaxf(v, xor16(v, g));
+  v = fmaxf(v, xor32(v, g));
   return v;
 }
 
@@ -120,16 +143,40 @@ NXD float grp_max(float v) {
 // of an image with row length W): input index k = 3 tap + ch over the taps in
 // raster order (h rows of 2h+1, then h to the left in row i); lane group g
 // gathers k = 4 kc + g for K-chunk kc. Outside the lane reads as 0.
+// A lane's tap offsets are packed, one byte per K-chunk (dy | dx << 2 | ch << 5),
+// into TapCodes once; unpacking them per pixel keeps them out of the register
+// budget of the persistent loops.
 template <int H_>
-NXD void gather(float (&ctx)[conv_chunks(H_)], const uint8_t* __restrict__ img, int W, int y0, int x0, int Hl,
-                int Wl, int i, int j, bool active, int g) {
-  constexpr int K = 2 * H_ + 1;
+struct TapCodes {
+  static constexpr int NW = (conv_chunks(H_) + 3) / 4;
+  uint32_t w[NW];
+  NXD void init(int g) {
+    constexpr int K = 2 * H_ + 1;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) w[t] = 0;
+#pragma unroll
+    for (int kc = 0; kc < conv_chunks(H_); ++kc) {
+      const int k = 4 * kc + g;
+      const int tap = k / 3, ch = k - 3 * (k / 3);
+      const int dy = tap < H_ * K ? tap / K : H_;
+      const int dx = tap < H_ * K ? tap - K * (tap / K) : tap - H_ * K;
+      w[kc >> 2] |= (uint32_t)(dy | (dx << 2) | (ch << 5)) << (8 * (kc & 3));
+    }
+  }
+  // an opaque copy per use: the unpacked offsets are not hoisted out of loops
+  NXD void refresh() {
+#pragma unroll
+    for (int t = 0; t < NW; ++t) asm volatile("" : "+v"(w[t]));
+  }
+};
+
+template <int H_>
+NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uint8_t* __restrict__ img, int W,
+                int y0, int x0, int Hl, int Wl, int i, int j, bool active) {
 #pragma unroll
   for (int kc = 0; kc < conv_chunks(H_); ++kc) {
-    const int k = 4 * kc + g;
-    const int tap = k / 3, ch = k - 3 * (k / 3);
-    const int dy = tap < H_ * K ? tap / K : H_;
-    const int dx = tap < H_ * K ? tap - K * (tap / K) : tap - H_ * K;
+    const uint32_t code = (tc.w[kc >> 2] >> (8 * (kc & 3))) & 0xffu;
+    const int dy = (int)(code & 3u), dx = (int)((code >> 2) & 7u), ch = (int)(code >> 5);
     const int y = i - H_ + dy, x = j - H_ + dx;
     const bool ok = active && y >= 0 && y < Hl && x >= 0 && x < Wl;
     float v = 0.0f;
@@ -265,18 +312,23 @@ NXD void mix_prep(const f4 (&hd)[HEAD_TILES], Mix& M, bool has2) {
 }
 
 // Mixture of channel c given the normalised values of the earlier channels:
-// weights, shifted means, inverse scales of this lane's slots.
+// weights, shifted means, inverse scales of this lane's slots. (c may be a
+// runtime value: the channel rows are selected, not indexed, so the mixture
+// stays in registers.)
 NXD void chan_params(const Mix& M, int c, float xr, float xg, float (&w)[3], float (&mu)[3], float (&is)[3]) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     w[j] = xexp(M.logw[j]);
-    is[j] = M.invs[c][j];
-    float m = M.mu[c][j];
-    if (c == 1) m = m + M.co[0][j] * xr;
-    if (c == 2) {
+    is[j] = c == 0 ? M.invs[0][j] : (c == 1 ? M.invs[1][j] : M.invs[2][j]);
+    float m;
+    if (c == 0) {
+      m = M.mu[0][j];
+    } else if (c == 1) {
+      m = M.mu[1][j] + M.co[0][j] * xr;
+    } else {
       const float t1 = M.co[1][j] * xr;
       const float t2 = M.co[2][j] * xg;
-      m = (m + t1) + t2;
+      m = (M.mu[2][j] + t1) + t2;
     }
     mu[j] = m;
   }

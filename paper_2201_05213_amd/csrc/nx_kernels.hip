@@ -15,7 +15,10 @@
 
 namespace nx {
 
-constexpr int NWAVES = 8;  // waves per persistent workgroup (all share the LDS weights)
+constexpr int NWAVES = 16;      // waves per full-image-pass workgroup (all share the LDS weights)
+constexpr int NWAVES_DEC = DECODE_WAVES;  // waves per decoder workgroup
+constexpr int PIV_WORDS = 256;            // per decoder wave: 16 pixels x 16 pivot CDF values
+static_assert(DECODE_LDS_EXTRA == NWAVES_DEC * PIV_WORDS * 4, "decoder LDS budget");
 
 NXD int find_img(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane) {
   int lo = 0, hi = n - 1;
@@ -27,11 +30,49 @@ NXD int find_img(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane
   return lo;
 }
 
+
 NXD uint32_t rd_u32(const uint8_t* p) {
   return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
 }
 
 NXD int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+NXD int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// the same search with every step wave-uniform (key must be wave-uniform)
+NXD int find_img_uniform(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane = true) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = uniform64(by_lane ? d[mid].lane_base : d[mid].tile_base);
+    if (b <= key) lo = mid; else hi = mid - 1;
+  }
+  return uniform(lo);
+}
+
+// Descriptor fields as wave-uniform values. Every lane loads the same
+// descriptor; saying so (readfirstlane) keeps all control flow that depends
+// on it uniform: the compiler then never splits a wave across the exits of the
+// persistent loops.
+NXD ImgDesc uniform_desc(const ImgDesc* __restrict__ p) {
+  ImgDesc D = *p;
+  D.px = (uint8_t*)uniform64((int64_t)D.px);
+  D.H = uniform(D.H);
+  D.W = uniform(D.W);
+  D.ph = uniform(D.ph);
+  D.pw = uniform(D.pw);
+  D.nlx = uniform(D.nlx);
+  D.nly = uniform(D.nly);
+  D.lane_base = uniform64(D.lane_base);
+  D.px_base = uniform64(D.px_base);
+  D.tile_base = uniform64(D.tile_base);
+  D.ntx = uniform(D.ntx);
+  D.slot_base = uniform64(D.slot_base);
+  return D;
+}
 
 // The weight image is never written after it is staged in LDS, so the
 // compiler would hoist every weight read out of the persistent loops and try
@@ -68,9 +109,12 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
   const bool has2 = g < 2;
   const int64_t gw = (int64_t)blockIdx.x * NWAVES + (threadIdx.x >> 6);
   const int64_t nwv = (int64_t)gridDim.x * NWAVES;
+  TapCodes<H_> tc;
+  tc.init(g);
   for (int64_t t = gw; t < A.n_tiles; t += nwv) {
-    const int n = find_img(A.desc, A.n_img, t, false);
-    const ImgDesc D = A.desc[n];
+    tc.refresh();
+    const int n = find_img_uniform(A.desc, A.n_img, t, false);
+    const ImgDesc D = uniform_desc(A.desc + n);
     const int64_t tt = t - D.tile_base;
     const int y = (int)(tt / D.ntx);
     const int xraw = (int)(tt - (int64_t)y * D.ntx) * 16 + p;
@@ -80,7 +124,7 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
     const int y0 = ly * D.ph, x0 = lx * D.pw;
     const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
     float ctx[conv_chunks(H_)];
-    gather<H_>(ctx, D.px, D.W, y0, x0, Hl, Wl, y - y0, x - x0, active, g);
+    gather<H_>(ctx, tc, D.px, D.W, y0, x0, Hl, Wl, y - y0, x - x0, active);
     f4 head[HEAD_TILES];
     net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
     Mix M;
@@ -327,43 +371,47 @@ struct ByteStage {
 };
 
 template <int H_, int C_>
-__device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lane) {
+__device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int64_t L, int lane) {
   const int p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
-  const int n = find_img(A.desc, A.n_img, L, true);
-  const ImgDesc D = A.desc[n];
+  const int n = find_img_uniform(A.desc, A.n_img, L);
+  const ImgDesc D = uniform_desc(A.desc + n);
   const int q = (int)(L - D.lane_base);
   const int nl = D.nlx * D.nly;
   const int ly = q / D.nlx, lx = q - ly * D.nlx;
   const int y0 = ly * D.ph, x0 = lx * D.pw;
   const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
-  const uint8_t* C = A.in + A.in_off[n];
-  const int64_t clen = (int64_t)(A.in_off[n + 1] - A.in_off[n]);
+  const uint8_t* C = A.in + uniform64((int64_t)A.in_off[n]);
+  const int64_t clen = uniform64((int64_t)(A.in_off[n + 1] - A.in_off[n]));
   const int64_t pay = HDR_BYTES + 4 * (int64_t)nl;
-  // header and lane table checks (every lane reads the same bytes)
+  // header and lane table checks (every lane reads the same bytes; the
+  // verdicts are made wave-uniform, and status is stored by every lane)
   bool ok = clen >= pay;
+  bool mismatch = false;
   if (ok) {
     const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
     ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION &&
          C[5] == (uint8_t)A.order && C[6] == (uint8_t)H_ && C[7] == CODER_RANS8 && rd_u32(C + 8) == (uint32_t)D.H &&
          rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
          (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
+    ok = uniform(ok ? 1 : 0) != 0;
     if (ok) {
       const uint64_t hsh = (uint64_t)rd_u32(C + 20) | ((uint64_t)rd_u32(C + 24) << 32);
-      if (hsh != A.model_hash) {
-        if (lane == 0) A.status[n] = ST_MISMATCH;
-        return;
-      }
+      mismatch = uniform(hsh != A.model_hash ? 1 : 0) != 0;
     }
+  }
+  if (mismatch) {
+    A.status[n] = ST_MISMATCH;
+    return;
   }
   uint32_t lend = 0, lstart = 0;
   if (ok) {
-    lend = rd_u32(C + HDR_BYTES + 4 * (int64_t)q);
-    lstart = q > 0 ? rd_u32(C + HDR_BYTES + 4 * (int64_t)(q - 1)) : 0u;
+    lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (int64_t)q));
+    lstart = q > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (int64_t)(q - 1))) : 0u;
     ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
   }
   if (!ok) {
-    if (lane == 0) A.status[n] = ST_CORRUPT;
+    A.status[n] = ST_CORRUPT;
     return;
   }
   ByteStage R;
@@ -377,6 +425,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lan
   const bool raster = A.order == 0;
   const int64_t ngroups = raster ? (int64_t)Hl * Wl : (int64_t)Wl + (int64_t)o * (Hl - 1);
   uint32_t* dump = A.sym_dump ? A.sym_dump + D.px_base * 3 : nullptr;
+  TapCodes<H_> tc;
+  tc.init(g);
 
   for (int64_t gi = 0; gi < ngroups; ++gi) {
     int ilo, ihi;
@@ -391,7 +441,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lan
       const bool active = p < na;
       const int j = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * i;
       float ctx[conv_chunks(H_)];
-      gather<H_>(ctx, img, D.W, y0, x0, Hl, Wl, i, j, active, g);
+      tc.refresh();
+      gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
       f4 head[HEAD_TILES];
       net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
       Mix M;
@@ -402,6 +453,17 @@ __device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lan
       for (int c = 0; c < 3; ++c) {
         float wc[3], mu[3], is[3];
         chan_params(M, c, xr, xg, wc, mu, is);
+        // pivot CDF values of every pixel of the group: cdf at k = 16 (j + 1),
+        // j = 0..14, and 2^16 for k = 256 (independent evaluations)
+#pragma unroll 3
+        for (int jp = 0; jp < 15; ++jp) {
+          const uint32_t v = cdf_quant(16 * (jp + 1), cdf_eval(16 * (jp + 1), wc, mu, is));
+          if (g == 0) piv[p * 16 + jp] = v;
+        }
+        if (g == 0) piv[p * 16 + 15] = CDF_TOTAL;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int pp = 0; pp < na; ++pp) {
           const int src = (g << 4) | pp;
           float bw[3], bm[3], bs[3];
@@ -412,39 +474,43 @@ __device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lan
             bs[k] = __shfl(is[k], src);
           }
           const uint32_t slot = x & 0xffffu;
-          // round 1: pivots k = 16 (p + 1)
-          const int k1 = 16 * (p + 1);
-          const float F1 = cdf_eval(min(k1, 255), bw, bm, bs);
-          const uint32_t c1 = p == 15 ? CDF_TOTAL : cdf_quant(k1, F1);
-          const int b = __popcll(__ballot(c1 <= slot) & 0xffffull);
-          // round 2: k = 16 b + p inside the bucket
+          // bucket: pivots of pixel pp at or below the slot
+          const uint32_t pv = piv[pp * 16 + p];
+          const int b = __popcll(__ballot(pv <= slot) & 0xffffull);
+          // inside the bucket: k = 16 b + p
           const int k2 = 16 * b + p;
           const float F2 = cdf_eval(max(k2, 1), bw, bm, bs);
           uint32_t c2 = cdf_quant(k2, F2);
-          const uint32_t cb = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)c1, b - 1);
-          if (p == 0) c2 = cb;
+          if (p == 0) c2 = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)pv, b - 1);
           const int cnt = __popcll(__ballot(c2 <= slot) & 0xffffull) - 1;
           const int s = 16 * b + cnt;
           const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
-          uint32_t next;
-          if (cnt < 15) next = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt + 1);
-          else next = b == 15 ? CDF_TOTAL : (uint32_t)__builtin_amdgcn_readlane((int)c1, b);
+          const uint32_t next = cnt < 15 ? (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt + 1)
+                                         : (uint32_t)__builtin_amdgcn_readlane((int)pv, b);
           const uint32_t freq = next - start;
           x = freq * (x >> 16) + slot - start;
           while (x < RANS_L && pos < R.len) {
             x = (x << 8) | R.get(pos, lane);
             ++pos;
           }
-          if (p == pp) xv[c] = s;
-          if (dump && lane == 0) {
+          if (p == pp) {
+            if (c == 0) xv[0] = s;
+            else if (c == 1) xv[1] = s;
+            else xv[2] = s;
+          }
+          if (dump) {  // every lane stores the same value
             const int ii = ts + pp;
-            const int jj = raster ? j : (int)gi - o * ii;
+            const int jj = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * ii;
             dump[((int64_t)(y0 + ii) * D.W + (x0 + jj)) * 3 + c] = start | (freq << 16);
           }
         }
-        if (c < 2) posterior(M, xv[c], mu, is, has2);
-        if (c == 0) xr = normalise(xv[0]);
-        if (c == 1) xg = normalise(xv[1]);
+        if (c == 0) {
+          posterior(M, xv[0], mu, is, has2);
+          xr = normalise(xv[0]);
+        } else if (c == 1) {
+          posterior(M, xv[1], mu, is, has2);
+          xg = normalise(xv[1]);
+        }
       }
       if (active && g == 0) {
         uint8_t* dst = img + ((int64_t)(y0 + i) * D.W + (x0 + j)) * 3;
@@ -456,21 +522,25 @@ __device__ void decode_lane(const DecArgs& A, const float* w, int64_t L, int lan
       __threadfence_block();
     }
   }
-  if (!(x == RANS_X0 && pos == R.len) && lane == 0) A.status[n] = ST_CORRUPT;
+  const bool clean = x == RANS_X0 && pos == R.len;
+  if (!clean) A.status[n] = ST_CORRUPT;
 }
 
 template <int H_, int C_>
-__global__ void __launch_bounds__(NWAVES * 64) k_decode(DecArgs A) {
+__global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
-  load_weights<NWAVES * 64>(w, A.w, A.wfloats);
+  load_weights<NWAVES_DEC * 64>(w, A.w, A.wfloats);
   const int lane = threadIdx.x & 63;
+  uint32_t* piv = (uint32_t*)(w + A.wfloats) + (threadIdx.x >> 6) * PIV_WORDS;
   for (;;) {
+    // one queue pop per wave, by its first active lane, broadcast
+    const int leader = uniform(lane);
     int L = 0;
-    if (lane == 0) L = atomicAdd(A.counter, 1);
+    if (lane == leader) L = atomicAdd(A.counter, 1);
     L = uniform(L);
     if ((int64_t)L >= A.n_lanes) break;
-    decode_lane<H_, C_>(A, w, L, lane);
+    decode_lane<H_, C_>(A, w, piv, L, lane);
   }
 }
 
@@ -520,10 +590,10 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
 
 template <int H_, int C_>
 static hipError_t decode_t(const DecArgs& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.wfloats * 4;
+  const size_t lds = (size_t)a.wfloats * 4 + (size_t)NWAVES_DEC * PIV_WORDS * 4;
   hipError_t e = allow_lds(k_decode<H_, C_>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode<H_, C_>), dim3(grid), dim3(NWAVES * 64), lds, s, a);
+  hipLaunchKernelGGL((k_decode<H_, C_>), dim3(grid), dim3(NWAVES_DEC * 64), lds, s, a);
   return hipGetLastError();
 }
 

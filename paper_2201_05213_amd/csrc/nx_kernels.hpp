@@ -70,6 +70,11 @@ struct DecArgs {
   uint32_t* sym_dump;      // nullable: (start | freq << 16) used per pixel/channel
 };
 
+// decoder workgroup shape: waves per workgroup and the LDS it needs beyond
+// the weight image (a pivot table per wave)
+constexpr int DECODE_WAVES = 12;
+constexpr int DECODE_LDS_EXTRA = DECODE_WAVES * 256 * 4;
+
 // host launchers (return hipError_t of the launch); h in {1,2,3}, C in {16,32,64}
 bool supported(int h, int C);
 hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s);

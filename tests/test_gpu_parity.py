@@ -149,8 +149,6 @@ def test_batch512_roundtrip_and_gap(models):
         assert (np.abs(got - ref) > 1).mean() <= 1e-4
 
 
-@pytest.mark.skip(reason="decoding a container with a flipped payload byte did not return on the GPU; "
-                         "cause not yet shown (see DESIGN.md, open issues) -- kept off the GPU until it is")
 def test_corrupt_and_mismatch_detected(models, nx):
     say("[gpu] corrupt containers")
     m, _, _ = models["A"]
