@@ -170,18 +170,35 @@ struct TapCodes {
   }
 };
 
+// global-memory view of a byte pointer (lets the compiler use global loads)
+typedef const __attribute__((address_space(1))) uint8_t* gbytes;
+NXD gbytes as_global(const uint8_t* p) { return (gbytes)p; }
+
+// Every tap is loaded from a position clamped into the lane (always in
+// bounds), then taps outside the lane are replaced by 0: no branch around the
+// loads, so all of them are in flight together.
 template <int H_>
-NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uint8_t* __restrict__ img, int W,
-                int y0, int x0, int Hl, int Wl, int i, int j, bool active) {
+NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uint8_t* img, int W, int y0, int x0,
+                int Hl, int Wl, int i, int j, bool active) {
+  const gbytes gimg = as_global(img);
+  uint32_t raw[conv_chunks(H_)];
 #pragma unroll
   for (int kc = 0; kc < conv_chunks(H_); ++kc) {
     const uint32_t code = (tc.w[kc >> 2] >> (8 * (kc & 3))) & 0xffu;
     const int dy = (int)(code & 3u), dx = (int)((code >> 2) & 7u), ch = (int)(code >> 5);
+    const int y = min(max(i - H_ + dy, 0), Hl - 1), x = min(max(j - H_ + dx, 0), Wl - 1);
+    raw[kc] = gimg[((int64_t)(y0 + y) * W + (x0 + x)) * 3 + ch];
+  }
+#pragma unroll
+  for (int kc = 0; kc < conv_chunks(H_); ++kc) {
+    const uint32_t code = (tc.w[kc >> 2] >> (8 * (kc & 3))) & 0xffu;
+    const int dy = (int)(code & 3u), dx = (int)((code >> 2) & 7u);
     const int y = i - H_ + dy, x = j - H_ + dx;
-    const bool ok = active && y >= 0 && y < Hl && x >= 0 && x < Wl;
-    float v = 0.0f;
-    if (ok) v = normalise(img[((int64_t)(y0 + y) * W + (x0 + x)) * 3 + ch]);
-    ctx[kc] = v;
+    // inside the lane, as a bit mask (no short-circuit, no branch)
+    const int ok = -(int)(((unsigned)y < (unsigned)Hl) & ((unsigned)x < (unsigned)Wl) & (unsigned)active);
+    // normalise() of the tap, with the numerator masked: padding is exactly 0
+    const int num = (2 * (int)raw[kc] - 255) & ok;
+    ctx[kc] = (float)num * (1.0f / 255.0f);
   }
 }
 
@@ -312,14 +329,19 @@ NXD void mix_prep(const f4 (&hd)[HEAD_TILES], Mix& M, bool has2) {
 }
 
 // Mixture of channel c given the normalised values of the earlier channels:
-// weights, shifted means, inverse scales of this lane's slots. (c may be a
+// weights, shifted means, inverse scales of this lane's slots, and the
+// sigmoid coefficients a = s log2(e), b = mu a used by cdf_eval. (c may be a
 // runtime value: the channel rows are selected, not indexed, so the mixture
 // stays in registers.)
-NXD void chan_params(const Mix& M, int c, float xr, float xg, float (&w)[3], float (&mu)[3], float (&is)[3]) {
+struct Chan {
+  float w[3], mu[3], is[3], a[3], b[3];
+};
+
+NXD void chan_params(const Mix& M, int c, float xr, float xg, Chan& K) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    w[j] = xexp(M.logw[j]);
-    is[j] = c == 0 ? M.invs[0][j] : (c == 1 ? M.invs[1][j] : M.invs[2][j]);
+    K.w[j] = xexp(M.logw[j]);
+    const float is = c == 0 ? M.invs[0][j] : (c == 1 ? M.invs[1][j] : M.invs[2][j]);
     float m;
     if (c == 0) {
       m = M.mu[0][j];
@@ -330,18 +352,27 @@ NXD void chan_params(const Mix& M, int c, float xr, float xg, float (&w)[3], flo
       const float t2 = M.co[2][j] * xg;
       m = (M.mu[2][j] + t1) + t2;
     }
-    mu[j] = m;
+    K.mu[j] = m;
+    K.is[j] = is;
+    K.a[j] = is * kLog2e;
+    K.b[j] = m * K.a[j];
   }
 }
 
-// Mixture CDF at bin edge k (1..255) as F = sum_m w_m sigmoid((B_k - mu_m) s_m),
+// Mixture CDF at bin edge k (1..255):
+//   F = sum_m w_m / (1 + 2^(b_m - B_k a_m)),  i.e. sum_m w_m sigmoid((B_k - mu_m) s_m),
 // the sum taken per lane group over its slots in order, then across groups.
-// Every lane of a pixel must call this with the same k (lane-group shuffles).
-NXD float cdf_eval(int k, const float (&w)[3], const float (&mu)[3], const float (&is)[3]) {
-  const float b = bin_edge(k);
+// The exponent is one fused multiply-add, monotone decreasing in k (a >= 0),
+// and the hardware exp2 and reciprocal are monotone, so F is monotone in k.
+// Every lane of a pixel must call this with the same k (lane-group swaps).
+NXD float cdf_eval(int k, const float (&w)[3], const float (&a)[3], const float (&b)[3]) {
+  const float e = bin_edge(k);
   float t[3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) t[j] = w[j] * xsigmoid((b - mu[j]) * is[j]);
+  for (int j = 0; j < 3; ++j) {
+    const float x = __builtin_amdgcn_exp2f(__builtin_fmaf(-e, a[j], b[j]));
+    t[j] = w[j] * __builtin_amdgcn_rcpf(1.0f + x);
+  }
   const float s = (t[0] + t[1]) + t[2];
   return grp_sum(s);
 }

@@ -138,29 +138,29 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
     const int64_t gpix = D.px_base + pix;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float wc[3], mu[3], is[3];
-      chan_params(M, c, xr, xg, wc, mu, is);
+      Chan K;
+      chan_params(M, c, xr, xg, K);
       if (A.mode == 0) {
-        const float Flo = cdf_eval(max(xv[c], 1), wc, mu, is);
-        const float Fhi = cdf_eval(min(xv[c] + 1, 255), wc, mu, is);
+        const float Flo = cdf_eval(max(xv[c], 1), K.w, K.a, K.b);
+        const float Fhi = cdf_eval(min(xv[c] + 1, 255), K.w, K.a, K.b);
         const uint32_t lo = xv[c] == 0 ? 0u : cdf_quant(xv[c], Flo);
         const uint32_t hi = xv[c] == 255 ? CDF_TOTAL : cdf_quant(xv[c] + 1, Fhi);
         if (active && g == 0) A.sym[gpix * 3 + c] = lo | ((hi - lo) << 16);
         bits += (float)CDF_BITS - __builtin_amdgcn_logf((float)(hi - lo));
-        if (c < 2) posterior(M, xv[c], mu, is, has2);
+        if (c < 2) posterior(M, xv[c], K.mu, K.is, has2);
       } else if (A.mode == 1) {
-        const float lp = posterior(M, xv[c], mu, is, has2);
+        const float lp = posterior(M, xv[c], K.mu, K.is, has2);
         bits += -lp * kLog2e;
       } else {
         for (int k = 1; k < 256; ++k) {
-          const uint32_t v = cdf_quant(k, cdf_eval(k, wc, mu, is));
+          const uint32_t v = cdf_quant(k, cdf_eval(k, K.w, K.a, K.b));
           if (active && g == 0) A.cdf[(gpix * 3 + c) * 257 + k] = (int32_t)v;
         }
         if (active && g == 0) {
           A.cdf[(gpix * 3 + c) * 257] = 0;
           A.cdf[(gpix * 3 + c) * 257 + 256] = (int32_t)CDF_TOTAL;
         }
-        if (c < 2) posterior(M, xv[c], mu, is, has2);
+        if (c < 2) posterior(M, xv[c], K.mu, K.is, has2);
       }
     }
     if (A.bits && active && g == 0) A.bits[gpix] = bits;
@@ -353,12 +353,15 @@ struct ByteStage {
   int64_t len, base;
   uint32_t word;
   NXD void fill(int64_t at, int lane) {
+    // clamped, unconditional loads; bytes past the end read as 0
     base = at;
+    const gbytes g = as_global(S);
     uint32_t v = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int64_t o = at + 4 * lane + b;
-      if (o < len) v |= (uint32_t)S[o] << (8 * b);
+      const uint32_t byte = g[o < len ? o : len - 1];
+      v |= (o < len ? byte : 0u) << (8 * b);
     }
     word = v;
   }
@@ -451,40 +454,64 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       float xr = 0.0f, xg = 0.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        float wc[3], mu[3], is[3];
-        chan_params(M, c, xr, xg, wc, mu, is);
+        Chan K;
+        chan_params(M, c, xr, xg, K);
         // pivot CDF values of every pixel of the group: cdf at k = 16 (j + 1),
         // j = 0..14, and 2^16 for k = 256 (independent evaluations)
-#pragma unroll 3
+#pragma unroll 5
         for (int jp = 0; jp < 15; ++jp) {
-          const uint32_t v = cdf_quant(16 * (jp + 1), cdf_eval(16 * (jp + 1), wc, mu, is));
+          const uint32_t v = cdf_quant(16 * (jp + 1), cdf_eval(16 * (jp + 1), K.w, K.a, K.b));
           if (g == 0) piv[p * 16 + jp] = v;
         }
         if (g == 0) piv[p * 16 + 15] = CDF_TOTAL;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int pp = 0; pp < na; ++pp) {
-          const int src = (g << 4) | pp;
-          float bw[3], bm[3], bs[3];
+        // serial pops; the next pixel's pivot row and mixture (which do not
+        // depend on the coder state) are fetched one symbol ahead
+        float nw[3], nA[3], nB[3];
+        uint32_t npv = 0;
+        {
+          const int src = g << 4;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            bw[k] = __shfl(wc[k], src);
-            bm[k] = __shfl(mu[k], src);
-            bs[k] = __shfl(is[k], src);
+            nw[k] = __shfl(K.w[k], src);
+            nA[k] = __shfl(K.a[k], src);
+            nB[k] = __shfl(K.b[k], src);
+          }
+          npv = piv[p];
+        }
+        for (int pp = 0; pp < na; ++pp) {
+          float bw[3], bA[3], bB[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            bw[k] = nw[k];
+            bA[k] = nA[k];
+            bB[k] = nB[k];
+          }
+          const uint32_t pv = npv;
+          if (pp + 1 < na) {
+            const int src = (g << 4) | (pp + 1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              nw[k] = __shfl(K.w[k], src);
+              nA[k] = __shfl(K.a[k], src);
+              nB[k] = __shfl(K.b[k], src);
+            }
+            npv = piv[(pp + 1) * 16 + p];
           }
           const uint32_t slot = x & 0xffffu;
-          // bucket: pivots of pixel pp at or below the slot
-          const uint32_t pv = piv[pp * 16 + p];
+          // bucket: pivots of pixel pp at or below the slot (pv of lane p =
+          // cdf at 16 (p + 1); lane 15 holds 2^16)
           const int b = __popcll(__ballot(pv <= slot) & 0xffffull);
-          // inside the bucket: k = 16 b + p
+          // inside the bucket: cdf at k = 16 b + p for p = 1..15; the bucket's
+          // lower bound (p = 0) is cdf at 16 b <= slot by construction
           const int k2 = 16 * b + p;
-          const float F2 = cdf_eval(max(k2, 1), bw, bm, bs);
-          uint32_t c2 = cdf_quant(k2, F2);
-          if (p == 0) c2 = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)pv, b - 1);
-          const int cnt = __popcll(__ballot(c2 <= slot) & 0xffffull) - 1;
+          const uint32_t c2 = cdf_quant(k2, cdf_eval(max(k2, 1), bw, bA, bB));
+          const int cnt = __popcll(__ballot(c2 <= slot) & 0xfffeull);
           const int s = 16 * b + cnt;
-          const uint32_t start = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
+          const uint32_t lo = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)pv, b - 1);
+          const uint32_t start = cnt == 0 ? lo : (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
           const uint32_t next = cnt < 15 ? (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt + 1)
                                          : (uint32_t)__builtin_amdgcn_readlane((int)pv, b);
           const uint32_t freq = next - start;
@@ -505,10 +532,10 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           }
         }
         if (c == 0) {
-          posterior(M, xv[0], mu, is, has2);
+          posterior(M, xv[0], K.mu, K.is, has2);
           xr = normalise(xv[0]);
         } else if (c == 1) {
-          posterior(M, xv[1], mu, is, has2);
+          posterior(M, xv[1], K.mu, K.is, has2);
           xg = normalise(xv[1]);
         }
       }
