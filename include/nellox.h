@@ -147,6 +147,40 @@ nellox_status nellox_debug_symbols(const nellox_model* m, int32_t n, const nello
 nellox_status nellox_debug_cdf(const nellox_model* m, const nellox_image* img, const nellox_opts* opts,
                                int32_t* cdf, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- training (the objective of Eq. 2: the model's code length, and its
+ * gradient; Sec. 2.1 model) ----
+ * These calls take the parameters directly instead of a model handle, so an
+ * optimiser can update them between calls:
+ *   dims = {h, C, n_blocks, n_mix = 10}: h in {1,2,3}, C in 1..64 (1..32 for
+ *          h = 1), n_blocks >= 0, within one workgroup's LDS;
+ *   params: device FP32 vector in the weight blob's tensor order
+ *          (nellox_param_count(dims) floats; masked conv taps are ignored and
+ *          get gradient 0);
+ *   imgs: device, n images of H x W x 3 uint8, contiguous (a batch of crops).
+ * Number of FP32 parameters of a model with these dims (-1 if invalid). */
+int64_t nellox_param_count(const int32_t dims[4]);
+
+/* Device workspace bytes for nellox_nll_fwd_train / nellox_nll_bwd on a
+ * batch of n images of H x W (0 if the arguments are invalid). About
+ * (3 (2 n_blocks + 1) C + 300) * 4 bytes per pixel. */
+size_t nellox_train_workspace_bytes(const int32_t dims[4], int32_t n, int32_t H, int32_t W);
+
+/* Forward: bits_per_img[k] (device, n doubles) = -log2 p(image k), the joint
+ * mixture likelihood of every pixel summed in FP64. Saves in ws what
+ * nellox_nll_bwd needs. */
+nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n,
+                                   int32_t H, int32_t W, double* bits_per_img, void* ws, size_t ws_bytes,
+                                   void* stream);
+
+/* Backward: grad_params (device, overwritten) = sum_k grad_bits[k] *
+ * d bits_k / d params, grad_bits: device, n floats. ws must still hold the
+ * state of the last nellox_nll_fwd_train with the same params, dims and
+ * images (no other call on ws in between). Deterministic: the same inputs
+ * give the same bits. */
+nellox_status nellox_nll_bwd(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n, int32_t H,
+                             int32_t W, const float* grad_bits, float* grad_params, void* ws, size_t ws_bytes,
+                             void* stream);
+
 const char* nellox_last_error(void);
 
 #ifdef __cplusplus

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnellox.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("nx_kernels.hip", "nx_capi.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("nx_kernels.hip", "nx_train.hip", "nx_capi.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

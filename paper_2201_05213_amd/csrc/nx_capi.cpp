@@ -65,71 +65,14 @@ struct nellox_model {
 namespace {
 
 // Device weight image in the MFMA operand layout (see nx_layout.hpp).
+// Weight image of a parameter vector (layout and index map in nx_layout.hpp;
+// the training kernels build the same image on the device from the same map).
 std::vector<float> weight_image(int h, int C, int Cp, int nb, const float* P) {
   const WeightLayout L = weight_layout(h, Cp, nb);
   std::vector<float> img((size_t)L.total, 0.0f);
-  const int K = 2 * h + 1, KC = conv_chunks(h), KQ = conv_quads(h), MT = Cp / 16;
-  std::vector<std::pair<int, int>> taps;
-  for (int dy = 0; dy <= h; ++dy)
-    for (int dx = 0; dx < K; ++dx)
-      if (dy < h || dx < h) taps.push_back({dy, dx});
-  const float* conv_w = P;
-  const float* conv_b = conv_w + (int64_t)C * 3 * K * K;
-  const float* blk = conv_b + C;
-  const float* head_w = blk + (int64_t)nb * (2LL * C * C + 2LL * C);
-  const float* head_b = head_w + (int64_t)NOUT * C;
-  // conv: row o, input k = 3 tap + ch
-  for (int mt = 0; mt < MT; ++mt)
-    for (int kq = 0; kq < KQ; ++kq)
-      for (int lane = 0; lane < 64; ++lane)
-        for (int q = 0; q < 4; ++q) {
-          const int kc = 4 * kq + q;
-          if (kc >= KC) continue;
-          const int o = 16 * mt + (lane & 15), k = 4 * kc + (lane >> 4);
-          float v = 0.0f;
-          if (o < C) {
-            const int tap = k / 3, ch = k % 3;
-            v = conv_w[(((int64_t)o * 3 + ch) * K + taps[tap].first) * K + taps[tap].second];
-          }
-          img[L.conv + (((int64_t)mt * KQ + kq) * 64 + lane) * 4 + q] = v;
-        }
-  auto put_1x1 = [&](int64_t base, int mt_out, auto row_src, const float* Wm) {
-    for (int mt = 0; mt < mt_out; ++mt)
-      for (int ct = 0; ct < MT; ++ct)
-        for (int lane = 0; lane < 64; ++lane)
-          for (int q = 0; q < 4; ++q) {
-            const int r = 16 * mt + (lane & 15), col = 16 * ct + 4 * (lane >> 4) + q;
-            const int src = row_src(r);
-            img[base + (((int64_t)mt * MT + ct) * 64 + lane) * 4 + q] =
-                (src >= 0 && col < C) ? Wm[(int64_t)src * C + col] : 0.0f;
-          }
-  };
-  auto ident = [C](int r) { return r < C ? r : -1; };
-  for (int b = 0; b < nb; ++b) {
-    const float* w1 = blk + (int64_t)b * (2LL * C * C + 2LL * C);
-    const float* b1 = w1 + (int64_t)C * C;
-    const float* w2 = b1 + C;
-    const float* b2 = w2 + (int64_t)C * C;
-    put_1x1(L.layer0 + (2LL * b) * L.layer_stride, MT, ident, w1);
-    put_1x1(L.layer0 + (2LL * b + 1) * L.layer_stride, MT, ident, w2);
-    for (int o = 0; o < C; ++o) {
-      img[L.bias_blocks + (2LL * b) * Cp + o] = b1[o];
-      img[L.bias_blocks + (2LL * b + 1) * Cp + o] = b2[o];
-    }
-  }
-  // head rows: MFMA row r = 16 mt + 4 g + v is slot s = 4 mt + v of lane group
-  // g, i.e. parameter s % 10 of component g + 4 (s / 10); parameter p of
-  // component m is head output 10 p + m
-  auto head_src = [](int r) {
-    const int mt = r / 16, g = (r % 16) / 4, v = r % 4;
-    const int s = 4 * mt + v, m = g + 4 * (s / 10), p = s % 10;
-    return (s < 30 && m < NMIX) ? 10 * p + m : -1;
-  };
-  put_1x1(L.head, HEAD_TILES, head_src, head_w);
-  for (int o = 0; o < C; ++o) img[L.bias_conv + o] = conv_b[o];
-  for (int r = 0; r < 16 * HEAD_TILES; ++r) {
-    const int src = head_src(r);
-    img[L.bias_head + r] = src >= 0 ? head_b[src] : 0.0f;
+  for (int64_t i = 0; i < L.total; ++i) {
+    const int64_t src = wimg_src(h, C, Cp, nb, i);
+    if (src >= 0) img[(size_t)i] = P[src];
   }
   return img;
 }
@@ -250,6 +193,107 @@ nellox_status run_pass(nellox_model* m, const Plan& P, uint8_t* ws, const WsLayo
   hipError_t e = launch_pass(m->h, m->Cp, a, grid, s);
   if (e != hipSuccess) return hip_fail(e, "full-image pass launch");
   return NELLOX_OK;
+}
+
+}  // namespace
+
+namespace {
+// ------------------------------------------------------------------ training plan
+struct TrainPlan {
+  int h, C, Cp, nb, KP;
+  int n, H, W, ntx;
+  int64_t npx, ntiles, chunk, nchunks, ngrad;
+  int64_t wfloats, wTfloats;
+  // workspace byte offsets
+  int64_t wimg, wimgT, bits, ctx, u, theta, delta, dtheta, partial, total;
+  // float offsets inside one gradient partial
+  int64_t off_conv, off_blocks, off_head, bias_conv, bias_blocks, bias_head;
+};
+
+constexpr int TRAIN_MAX_BLOCKS = 4;      // 2 n_blocks 1x1 layers in one gradient launch
+constexpr int64_t TRAIN_CHUNK = 512;     // pixels per weight-gradient partial
+
+int device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  return v;
+}
+
+int device_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  return v > 0 ? v : 1;
+}
+
+nellox_status train_plan(const int32_t* dims, int32_t n, int32_t H, int32_t W, TrainPlan& T, bool check_lds) {
+  if (!dims) return fail(NELLOX_E_ARG, "dims is null");
+  const int h = dims[0], C = dims[1], nb = dims[2];
+  if (dims[3] != NMIX) return fail(NELLOX_E_ARG, "n_mix must be 10");
+  if (h < 1 || h > 3 || C < 1 || C > 64 || nb < 0 || nb > TRAIN_MAX_BLOCKS)
+    return fail(NELLOX_E_ARG, "dims out of range (h 1..3, C 1..64, n_blocks 0..4)");
+  const int Cp = (C + 15) / 16 * 16;
+  if (!supported(h, Cp)) return fail(NELLOX_E_UNSUPPORTED, "no kernel for these dims");
+  if (n < 1 || H < 1 || W < 1 || H > 65535 || W > 65535) return fail(NELLOX_E_ARG, "n, H, W out of range");
+  T.h = h; T.C = C; T.Cp = Cp; T.nb = nb;
+  T.KP = (3 * n_taps(h) + 15) / 16 * 16;
+  T.n = n; T.H = H; T.W = W; T.ntx = (W + 15) / 16;
+  T.npx = (int64_t)n * H * W;
+  T.ntiles = (int64_t)n * H * T.ntx;
+  T.chunk = TRAIN_CHUNK;
+  T.nchunks = (T.npx + T.chunk - 1) / T.chunk;
+  T.wfloats = weight_layout(h, Cp, nb).total;
+  T.wTfloats = weightT_layout(Cp, nb).total;
+  if (check_lds) {
+    const int64_t lim = device_lds_limit();
+    if (T.wfloats * 4 > lim || T.wTfloats * 4 > lim)
+      return fail(NELLOX_E_UNSUPPORTED, "weights exceed the LDS of one workgroup");
+  }
+  T.off_conv = 0;
+  T.off_blocks = (int64_t)Cp * T.KP;
+  T.off_head = T.off_blocks + 2LL * nb * Cp * Cp;
+  T.bias_conv = T.off_head + 16LL * HEAD_TILES * Cp;
+  T.bias_blocks = T.bias_conv + Cp;
+  T.bias_head = T.bias_blocks + 2LL * nb * Cp;
+  T.ngrad = T.bias_head + 16 * HEAD_TILES;
+  int64_t o = 0;
+  auto seg = [&o](int64_t bytes) { const int64_t at = o; o = align256(o + std::max<int64_t>(bytes, 1)); return at; };
+  T.wimg = seg(4 * T.wfloats);
+  T.wimgT = seg(4 * T.wTfloats);
+  T.bits = seg(4 * T.npx);
+  T.ctx = seg(4 * T.npx * T.KP);
+  T.u = seg(4 * (2LL * nb + 1) * T.npx * Cp);
+  T.theta = seg(4 * T.npx * 16 * HEAD_TILES);
+  T.delta = seg(4 * (2LL * nb + 1) * T.npx * Cp);
+  T.dtheta = seg(4 * T.npx * 16 * HEAD_TILES);
+  T.partial = seg(4 * T.nchunks * T.ngrad);
+  T.total = o;
+  return NELLOX_OK;
+}
+
+TrainArgs train_args(const TrainPlan& T, const uint8_t* imgs, uint8_t* ws, const float* grad_bits) {
+  TrainArgs a{};
+  a.imgs = imgs;
+  a.n = T.n; a.H = T.H; a.W = T.W; a.ntx = T.ntx;
+  a.npx = T.npx; a.n_tiles = T.ntiles;
+  a.nb = T.nb; a.Cp = T.Cp; a.KP = T.KP;
+  a.wimg = (const float*)(ws + T.wimg);
+  a.wimgT = (const float*)(ws + T.wimgT);
+  a.wfloats = T.wfloats; a.wTfloats = T.wTfloats;
+  a.bits = (float*)(ws + T.bits);
+  a.ctx = (float*)(ws + T.ctx);
+  a.u = (float*)(ws + T.u);
+  a.theta = (float*)(ws + T.theta);
+  a.delta = (float*)(ws + T.delta);
+  a.dtheta = (float*)(ws + T.dtheta);
+  a.grad_bits = grad_bits;
+  return a;
+}
+
+int train_grid(const TrainPlan& T) {
+  const int64_t need = (T.ntiles + 15) / 16;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(need, device_cus()));
 }
 
 }  // namespace
@@ -520,6 +564,83 @@ nellox_status nellox_debug_cdf(const nellox_model* mc, const nellox_image* img, 
   uint8_t* w8 = (uint8_t*)ws;
   if ((st = upload_plan(m, P, w8, W, s))) return st;
   return run_pass(m, P, w8, W, 2, nullptr, nullptr, cdf, s);
+}
+
+int64_t nellox_param_count(const int32_t dims[4]) {
+  if (!dims || dims[0] < 1 || dims[0] > 3 || dims[1] < 1 || dims[2] < 0 || dims[3] != NMIX) return -1;
+  return param_layout(dims[0], dims[1], dims[2]).total;
+}
+
+size_t nellox_train_workspace_bytes(const int32_t dims[4], int32_t n, int32_t H, int32_t W) {
+  TrainPlan T;
+  if (train_plan(dims, n, H, W, T, false) != NELLOX_OK) return 0;
+  return (size_t)T.total;
+}
+
+nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n,
+                                   int32_t H, int32_t W, double* bits_per_img, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  TrainPlan T;
+  nellox_status st = train_plan(dims, n, H, W, T, true);
+  if (st) return st;
+  if (!params || !imgs || !bits_per_img || !ws) return fail(NELLOX_E_ARG, "null pointer argument");
+  if ((int64_t)ws_bytes < T.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* w8 = (uint8_t*)ws;
+  hipError_t e = launch_swizzle(params, T.h, T.C, T.Cp, T.nb, (float*)(w8 + T.wimg), T.wfloats,
+                                (float*)(w8 + T.wimgT), T.wTfloats, s);
+  if (e != hipSuccess) return hip_fail(e, "weight image launch");
+  const TrainArgs a = train_args(T, imgs, w8, nullptr);
+  e = launch_train_fwd(T.h, T.Cp, a, train_grid(T), s);
+  if (e != hipSuccess) return hip_fail(e, "training forward launch");
+  e = launch_bits_img(a.bits, T.n, (int64_t)T.H * T.W, bits_per_img, s);
+  if (e != hipSuccess) return hip_fail(e, "bits reduction launch");
+  return NELLOX_OK;
+}
+
+nellox_status nellox_nll_bwd(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n, int32_t H,
+                             int32_t W, const float* grad_bits, float* grad_params, void* ws, size_t ws_bytes,
+                             void* stream) {
+  TrainPlan T;
+  nellox_status st = train_plan(dims, n, H, W, T, true);
+  if (st) return st;
+  if (!params || !imgs || !grad_bits || !grad_params || !ws) return fail(NELLOX_E_ARG, "null pointer argument");
+  if ((int64_t)ws_bytes < T.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* w8 = (uint8_t*)ws;
+  hipError_t e = launch_swizzle(params, T.h, T.C, T.Cp, T.nb, (float*)(w8 + T.wimg), T.wfloats,
+                                (float*)(w8 + T.wimgT), T.wTfloats, s);
+  if (e != hipSuccess) return hip_fail(e, "weight image launch");
+  const TrainArgs a = train_args(T, imgs, w8, grad_bits);
+  e = launch_train_bwd(T.h, T.Cp, a, train_grid(T), s);
+  if (e != hipSuccess) return hip_fail(e, "training backward launch");
+  WgradArgs g{};
+  g.npx = T.npx; g.chunk = T.chunk; g.nchunks = T.nchunks; g.ngrad = T.ngrad;
+  g.partial = (float*)(w8 + T.partial);
+  const int64_t pc = T.npx * T.Cp;
+  // first layer: deltas of a_0, inputs = the causal taps
+  g.layer[0] = WgradLayer{a.delta, a.ctx, T.Cp, T.KP, T.off_conv, T.bias_conv};
+  e = launch_wgrad(T.Cp / 16, T.KP / 16, g, 1, s);
+  if (e != hipSuccess) return hip_fail(e, "first-layer gradient launch");
+  // 1x1 layers: layer l (W1 of block l/2 or W2) has delta l + 1 and input u_l
+  for (int l = 0; l < 2 * T.nb; ++l)
+    g.layer[l] = WgradLayer{a.delta + (l + 1) * pc, a.u + l * pc, T.Cp, T.Cp, T.off_blocks + (int64_t)l * T.Cp * T.Cp,
+                            T.bias_blocks + (int64_t)l * T.Cp};
+  e = launch_wgrad(T.Cp / 16, T.Cp / 16, g, 2 * T.nb, s);
+  if (e != hipSuccess) return hip_fail(e, "block gradient launch");
+  g.layer[0] = WgradLayer{a.dtheta, a.u + 2LL * T.nb * pc, 16 * HEAD_TILES, T.Cp, T.off_head, T.bias_head};
+  e = launch_wgrad(HEAD_TILES, T.Cp / 16, g, 1, s);
+  if (e != hipSuccess) return hip_fail(e, "head gradient launch");
+  GradReduceArgs r{};
+  r.h = T.h; r.C = T.C; r.Cp = T.Cp; r.nb = T.nb; r.KP = T.KP;
+  r.off_conv = T.off_conv; r.off_blocks = T.off_blocks; r.off_head = T.off_head;
+  r.bias_conv = T.bias_conv; r.bias_blocks = T.bias_blocks; r.bias_head = T.bias_head;
+  r.nchunks = T.nchunks; r.ngrad = T.ngrad;
+  r.partial = g.partial;
+  r.grad = grad_params;
+  e = launch_grad_reduce(r, s);
+  if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+  return NELLOX_OK;
 }
 
 }  // extern "C"

@@ -203,6 +203,16 @@ NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uin
 }
 
 // ------------------------------------------------------------------ network
+// The weight image is never written after it is staged in LDS, so the
+// compiler would hoist every weight read out of the persistent loops and try
+// to keep the whole network in registers. An offset it cannot see through
+// (always 0) keeps the reads next to their MFMAs.
+NXD const float* lds_weights(const float* w) {
+  int zero = 0;
+  asm volatile("" : "+s"(zero));
+  return w + zero;
+}
+
 // One 1x1 layer: out[mt] (pre-initialised with the bias) += W in, K-chunks in
 // the order (ct, q) = (0,0), (0,1), ..., (C/16-1, 3).
 template <int MT_OUT, int CT_IN>
@@ -228,11 +238,20 @@ NXD void bias_init(f4 (&a)[N], const float* __restrict__ b, int g) {
     for (int v = 0; v < 4; ++v) a[mt][v] = b[16 * mt + 4 * g + v];
 }
 
+// Receives each post-activation tensor of the network (for the backward
+// pass); the default discards them.
+struct NoSink {
+  template <int N>
+  NXD void operator()(int, const f4 (&)[N]) const {}
+};
+
 // Network of a 16-pixel tile: head[8] receives the 128 (permuted) head rows.
 // w points at the weight image (LDS). ctx is this lane's conv B operand.
-template <int H_, int C_>
+// sink(l, u) sees the layer inputs u = elu(.) in order: l = 2b is the input of
+// block b's first 1x1 layer, 2b + 1 of its second, 2 nb of the head.
+template <int H_, int C_, class Sink = NoSink>
 NXD void net_forward(const float* __restrict__ w, int nb, const float (&ctx)[conv_chunks(H_)], f4 (&head)[HEAD_TILES],
-                     int lane) {
+                     int lane, const Sink& sink = Sink()) {
   constexpr int MT = C_ / 16;
   constexpr int KC = conv_chunks(H_), KQ = conv_quads(H_);
   const WeightLayout L = weight_layout(H_, C_, 0);
@@ -265,12 +284,14 @@ NXD void net_forward(const float* __restrict__ w, int nb, const float (&ctx)[con
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) u[mt][v] = xelu(a[mt][v]);
+    sink(2 * b, u);
     bias_init(z, bias_blk + (int64_t)(2 * b) * C_, g);
     layer_mm<MT, MT>(w + L.layer0 + (int64_t)(2 * b) * layer_stride, u, z, lane);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) u[mt][v] = xelu(z[mt][v]);
+    sink(2 * b + 1, u);
     bias_init(z, bias_blk + (int64_t)(2 * b + 1) * C_, g);
     layer_mm<MT, MT>(w + L.layer0 + (int64_t)(2 * b + 1) * layer_stride, u, z, lane);
 #pragma unroll
@@ -281,6 +302,7 @@ NXD void net_forward(const float* __restrict__ w, int nb, const float (&ctx)[con
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) u[mt][v] = xelu(a[mt][v]);
+  sink(2 * nb, u);
   bias_init(head, bias_head, g);
   layer_mm<HEAD_TILES, MT>(w_head, u, head, lane);
 }

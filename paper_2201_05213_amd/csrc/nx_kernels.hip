@@ -74,15 +74,6 @@ NXD ImgDesc uniform_desc(const ImgDesc* __restrict__ p) {
   return D;
 }
 
-// The weight image is never written after it is staged in LDS, so the
-// compiler would hoist every weight read out of the persistent loops and try
-// to keep the whole network in registers. An offset it cannot see through
-// (always 0) keeps the reads next to their MFMAs.
-NXD const float* lds_weights(const float* w) {
-  int zero = 0;
-  asm volatile("" : "+s"(zero));
-  return w + zero;
-}
 NXD uint32_t uniform_u(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
 // rows active at wavefront step t of an Hl x Wl lane, step offset o = h + 1

@@ -70,6 +70,46 @@ struct DecArgs {
   uint32_t* sym_dump;      // nullable: (start | freq << 16) used per pixel/channel
 };
 
+// Training objective and gradient (nx_train.hip). n images of H x W, all
+// pixel tensors pixel-major.
+struct TrainArgs {
+  const uint8_t* imgs;     // n x H x W x 3
+  int n, H, W, ntx;        // ntx = ceil(W / 16)
+  int64_t npx, n_tiles;    // n H W, n H ntx
+  int nb, Cp, KP;          // KP = conv inputs padded to a multiple of 16
+  const float* wimg;       // forward weight image
+  const float* wimgT;      // transposed weight image
+  int64_t wfloats, wTfloats;
+  float* bits;             // [npx] continuous bits per pixel
+  float* ctx;              // [npx][KP] conv inputs (normalised taps)
+  float* u;                // [2 nb + 1][npx][Cp] inputs of the 1x1 layers and the head
+  float* theta;            // [npx][128] head rows
+  float* delta;            // [2 nb + 1][npx][Cp] output deltas: first layer, then per block W1, W2
+  float* dtheta;           // [npx][128] head-row deltas
+  const float* grad_bits;  // [n] d loss / d bits of image n
+};
+
+struct WgradLayer {
+  const float* delta;      // [npx][ld_delta]
+  const float* in;         // [npx][ld_in]
+  int ld_delta, ld_in;
+  int64_t w_off, b_off;    // offsets of this layer's dW [rows][cols] and db in a partial
+};
+
+struct WgradArgs {
+  WgradLayer layer[8];     // indexed by blockIdx.y
+  int64_t npx, chunk, nchunks, ngrad;
+  float* partial;          // [nchunks][ngrad]
+};
+
+struct GradReduceArgs {
+  int h, C, Cp, nb, KP;
+  int64_t off_conv, off_blocks, off_head, bias_conv, bias_blocks, bias_head;
+  int64_t nchunks, ngrad;
+  const float* partial;
+  float* grad;             // parameter vector layout
+};
+
 // decoder workgroup shape: waves per workgroup and the LDS it needs beyond
 // the weight image (a pivot table per wave)
 constexpr int DECODE_WAVES = 12;
@@ -83,5 +123,14 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s);
 hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s);
+
+constexpr int TRAIN_BLOCK = 16 * 64;  // threads per workgroup of the per-tile training kernels
+hipError_t launch_swizzle(const float* params, int h, int C, int Cp, int nb, float* wimg, int64_t nw, float* wimgT,
+                          int64_t nwT, hipStream_t s);
+hipError_t launch_train_fwd(int h, int Cp, const TrainArgs& a, int grid, hipStream_t s);
+hipError_t launch_train_bwd(int h, int Cp, const TrainArgs& a, int grid, hipStream_t s);
+hipError_t launch_wgrad(int MO, int KI, const WgradArgs& a, int nlayers, hipStream_t s);
+hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t s);
+hipError_t launch_bits_img(const float* bits, int n, int64_t per_img, double* out, hipStream_t s);
 
 }  // namespace nx

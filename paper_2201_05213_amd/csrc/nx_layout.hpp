@@ -1,7 +1,10 @@
 // nx_layout.hpp -- data layouts shared by the host runtime and the kernels:
 // the device weight image, per-image plan descriptors, the container header.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#define NXHD __host__ __device__ inline
 
 namespace nx {
 
@@ -71,5 +74,142 @@ constexpr uint8_t CODER_RANS8 = 1;  // byte-renormalising rANS, L=2^23, M=2^16, 
 
 // Lane slot for the rANS encoder: at most 2 bytes per symbol, 4 flush bytes.
 inline constexpr int64_t lane_slot_bytes(int64_t px) { return 6 * px + 8; }
+
+// ------------------------------------------------------------------ parameters
+// Offsets of the model tensors in the flat FP32 parameter vector, which is the
+// weight blob's tensor order: conv_w[C][3][2h+1][2h+1], conv_b[C], per block
+// {w1[C][C], b1[C], w2[C][C], b2[C]}, head_w[100][C], head_b[100].
+struct ParamLayout {
+  int h, C, nb;
+  int64_t conv_w, conv_b, blocks, block_stride, head_w, head_b, total;
+};
+
+NXHD constexpr ParamLayout param_layout(int h, int C, int nb) {
+  ParamLayout P{};
+  P.h = h; P.C = C; P.nb = nb;
+  const int64_t K = 2 * h + 1;
+  P.conv_w = 0;
+  P.conv_b = (int64_t)C * 3 * K * K;
+  P.blocks = P.conv_b + C;
+  P.block_stride = 2 * (int64_t)C * C + 2 * (int64_t)C;
+  P.head_w = P.blocks + (int64_t)nb * P.block_stride;
+  P.head_b = P.head_w + (int64_t)NOUT * C;
+  P.total = P.head_b + NOUT;
+  return P;
+}
+
+// live tap t of the masked first kernel (Eq. 3): taps in raster order, h full
+// rows of 2h+1 above the pixel, then h to its left
+NXHD void tap_of(int h, int t, int& dy, int& dx) {
+  const int K = 2 * h + 1;
+  if (t < h * K) { dy = t / K; dx = t - K * (t / K); }
+  else { dy = h; dx = t - h * K; }
+}
+// inverse: tap index of kernel position (dy, dx), or -1 where it is masked
+NXHD int tap_index(int h, int dy, int dx) {
+  const int K = 2 * h + 1;
+  if (dy < h) return dy * K + dx;
+  if (dy == h && dx < h) return h * K + dx;
+  return -1;
+}
+
+// Head MFMA row r (0..127) holds slot s = 4 (r/16) + r%4 of lane group
+// g = (r%16)/4: parameter s%10 of mixture component g + 4 (s/10), which is
+// head output 10 (s%10) + component. Returns -1 for padding rows.
+NXHD int head_row_src(int r) {
+  const int mt = r / 16, g = (r % 16) / 4, v = r % 4;
+  const int s = 4 * mt + v, m = g + 4 * (s / 10), p = s % 10;
+  return (s < 30 && m < NMIX) ? 10 * p + m : -1;
+}
+// inverse of head_row_src
+NXHD int head_row_of(int src) {
+  const int p = src / 10, m = src % 10;
+  const int s = 10 * (m / 4) + p, g = m % 4;
+  return 16 * (s / 4) + 4 * g + (s % 4);
+}
+
+// Source of weight-image float idx in the parameter vector, or -1 (zero).
+// C = model channels, Cp = C rounded up to 16 (the image's channel count).
+NXHD int64_t wimg_src(int h, int C, int Cp, int nb, int64_t idx) {
+  const WeightLayout L = weight_layout(h, Cp, nb);
+  const ParamLayout P = param_layout(h, C, nb);
+  const int MT = Cp / 16, K = 2 * h + 1, KQ = conv_quads(h), KC = conv_chunks(h);
+  if (idx < 0 || idx >= L.total) return -1;
+  if (idx < L.layer0) {
+    const int q = (int)(idx % 4), lane = (int)((idx / 4) % 64), kq = (int)((idx / 256) % KQ);
+    const int mt = (int)(idx / (256 * (int64_t)KQ));
+    const int kc = 4 * kq + q, o = 16 * mt + (lane & 15), k = 4 * kc + (lane >> 4);
+    if (kc >= KC || o >= C) return -1;
+    int dy, dx;
+    tap_of(h, k / 3, dy, dx);
+    return P.conv_w + (((int64_t)o * 3 + k % 3) * K + dy) * K + dx;
+  }
+  if (idx < L.bias_conv) {
+    const bool head = idx >= L.head;
+    const int64_t rel = head ? idx - L.head : (idx - L.layer0) % L.layer_stride;
+    const int q = (int)(rel % 4), lane = (int)((rel / 4) % 64), ct = (int)((rel / 256) % MT);
+    const int mt = (int)(rel / (256 * (int64_t)MT));
+    const int row = 16 * mt + (lane & 15), col = 16 * ct + 4 * (lane >> 4) + q;
+    if (col >= C) return -1;
+    if (head) {
+      const int src = head_row_src(row);
+      return src < 0 ? -1 : P.head_w + (int64_t)src * C + col;
+    }
+    if (row >= C) return -1;
+    const int64_t layer = (idx - L.layer0) / L.layer_stride;
+    return P.blocks + (layer / 2) * P.block_stride + (layer % 2) * ((int64_t)C * C + C) + (int64_t)row * C + col;
+  }
+  if (idx < L.bias_blocks) {
+    const int o = (int)(idx - L.bias_conv);
+    return o < C ? P.conv_b + o : -1;
+  }
+  if (idx < L.bias_head) {
+    const int64_t rel = idx - L.bias_blocks, layer = rel / Cp;
+    const int o = (int)(rel % Cp);
+    return o < C ? P.blocks + (layer / 2) * P.block_stride + (layer % 2) * ((int64_t)C * C + C) + (int64_t)C * C + o
+                 : -1;
+  }
+  const int src = head_row_src((int)(idx - L.bias_head));
+  return src < 0 ? -1 : P.head_b + src;
+}
+
+// Transposed weight image for the backward pass (input gradients of the 1x1
+// layers and the head): with the forward's D layout as the B operand, the
+// A operand of output tile ct (input channels) and K-chunk (mt, v) is
+//   [ct][mt][lane][v] = W[16 mt + 4 (lane/16) + v][16 ct + lane%16]
+// per 1x1 layer (2 nb of them), then the head (8 row tiles, permuted rows).
+struct WeightTLayout {
+  int64_t layer0, layer_stride, head, total;
+};
+NXHD constexpr WeightTLayout weightT_layout(int Cp, int nb) {
+  WeightTLayout T{};
+  const int64_t mt = Cp / 16;
+  T.layer0 = 0;
+  T.layer_stride = mt * mt * 256;
+  T.head = 2 * (int64_t)nb * T.layer_stride;
+  T.total = T.head + mt * HEAD_TILES * 256;
+  return T;
+}
+
+NXHD int64_t wimgT_src(int h, int C, int Cp, int nb, int64_t idx) {
+  const WeightTLayout T = weightT_layout(Cp, nb);
+  const ParamLayout P = param_layout(h, C, nb);
+  const int MT = Cp / 16;
+  if (idx < 0 || idx >= T.total) return -1;
+  const bool head = idx >= T.head;
+  const int64_t rel = head ? idx - T.head : idx % T.layer_stride;
+  const int KT = head ? HEAD_TILES : MT;  // K-chunk tiles (forward output tiles)
+  const int v = (int)(rel % 4), lane = (int)((rel / 4) % 64), mt = (int)((rel / 256) % KT);
+  const int ct = (int)(rel / (256 * (int64_t)KT));
+  const int row = 16 * mt + 4 * (lane >> 4) + v, col = 16 * ct + (lane & 15);
+  if (col >= C) return -1;
+  if (head) {
+    const int src = head_row_src(row);
+    return src < 0 ? -1 : P.head_w + (int64_t)src * C + col;
+  }
+  if (row >= C) return -1;
+  const int64_t layer = idx / T.layer_stride;
+  return P.blocks + (layer / 2) * P.block_stride + (layer % 2) * ((int64_t)C * C + C) + (int64_t)row * C + col;
+}
 
 }  // namespace nx

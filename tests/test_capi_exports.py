@@ -69,8 +69,40 @@ def test_host_only_calls(lib):
     assert L.nellox_peek(buf, 31, ctypes.byref(H), ctypes.byref(W), ctypes.byref(oo)) == 4
 
 
+def test_training_host_calls(lib):
+    from paper_2201_05213_amd import _lib, blob
+
+    L = _lib.load()
+    for h, C, nb in [(3, 64, 2), (3, 32, 1), (2, 32, 1), (3, 8, 1), (1, 16, 0)]:
+        d = (ctypes.c_int32 * 4)(h, C, nb, 10)
+        assert L.nellox_param_count(d) == blob.param_count(h, C, nb)
+        assert L.nellox_train_workspace_bytes(d, 4, 32, 32) > 4 * 4 * 32 * 32 * (3 * (2 * nb + 1) * C)
+    for bad in [(0, 32, 1, 10), (3, 32, 1, 9), (4, 16, 0, 10)]:
+        d = (ctypes.c_int32 * 4)(*bad)
+        assert L.nellox_param_count(d) == -1 or bad[0] == 4
+        assert L.nellox_train_workspace_bytes(d, 4, 32, 32) == 0
+    d = (ctypes.c_int32 * 4)(3, 64, 2, 10)
+    assert L.nellox_train_workspace_bytes(d, 0, 32, 32) == 0
+    assert L.nellox_train_workspace_bytes(d, 4, 0, 32) == 0
+
+
+def test_blob_round_trip():
+    import synth
+    from paper_2201_05213_amd import blob
+
+    for name in ("A", "B", "C", "tiny"):
+        b, dims = synth.model_blob(name)
+        d, p = blob.params_from_blob(b)
+        assert d == (dims["h"], dims["C"], dims["n_blocks"], 10)
+        assert blob.blob_from_params(d, p) == b
+    b, _ = synth.model_blob("tiny")
+    with pytest.raises(ValueError):
+        blob.params_from_blob(b[:-1] + bytes([b[-1] ^ 1]))
+
+
 def test_product_has_no_cpu_fallback():
     # the binding imports only the HIP library; the oracle is test-only
-    src = open(os.path.join(ROOT, "paper_2201_05213_amd", "__init__.py")).read()
-    src += open(os.path.join(ROOT, "paper_2201_05213_amd", "_lib.py")).read()
+    src = ""
+    for f in ("__init__.py", "_lib.py", "train.py", "blob.py"):
+        src += open(os.path.join(ROOT, "paper_2201_05213_amd", f)).read()
     assert "oracle" not in src and "synth" not in src

@@ -1,0 +1,169 @@
+"""GPU parity of the training objective and its hand-written gradient.
+
+The HIP path (nellox_nll_fwd_train / nellox_nll_bwd through the C ABI)
+against the FP64 torch reference (oracle/torch_ref.py, itself pinned to
+finite differences and to the C oracle on the CPU). Bars: code length
+within 1e-5 relative; gradient within 1e-4 relative (norm of the
+difference over the norm of the reference, over the whole vector and per
+tensor).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import torch_ref
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4
+BITS_TOL = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tr():
+    from paper_2201_05213_amd import blob, train
+
+    torch.cuda.set_device(0)
+    return train, blob
+
+
+def model(name, blob):
+    b, _ = synth.model_blob(name)
+    return blob.params_from_blob(b)
+
+
+def crops(n, side, seed):
+    pool = synth.training_pool(n=32)
+    return synth.training_crops(pool, n, side, np.random.Generator(np.random.PCG64(seed)))
+
+
+def gpu_bits_grad(train, dims, params, imgs, weights):
+    p = torch.from_numpy(params).cuda().requires_grad_(True)
+    x = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
+    bits = train.nll_bits(p, dims, x)
+    (bits * torch.as_tensor(weights, dtype=torch.float64, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    return bits.detach().cpu().numpy(), p.grad.detach().cpu().numpy().astype(np.float64)
+
+
+def ref_bits_grad(dims, params, imgs, weights):
+    h, C, nb, _ = dims
+    bits, g = torch_ref.nll_grad(torch.from_numpy(params.astype(np.float64)), h, C, nb,
+                                 torch.from_numpy(np.ascontiguousarray(imgs)), weights)
+    return bits.numpy(), g.numpy()
+
+
+def tensor_slices(dims):
+    h, C, nb, _ = dims
+    K = 2 * h + 1
+    out, o = [], 0
+    for name, n in [("conv_w", C * 3 * K * K), ("conv_b", C)] + \
+            sum([[(f"w1_{b}", C * C), (f"b1_{b}", C), (f"w2_{b}", C * C), (f"b2_{b}", C)] for b in range(nb)], []) + \
+            [("head_w", 100 * C), ("head_b", 100)]:
+        out.append((name, slice(o, o + n)))
+        o += n
+    return out
+
+
+def compare(dims, params, imgs, weights, tr, label):
+    train, _ = tr
+    gb, gg = gpu_bits_grad(train, dims, params, imgs, weights)
+    rb, rg = ref_bits_grad(dims, params, imgs, weights)
+    bits_err = float(np.max(np.abs(gb - rb) / np.abs(rb)))
+    err = float(np.linalg.norm(gg - rg) / np.linalg.norm(rg))
+    per = {n: float(np.linalg.norm(gg[s] - rg[s]) / max(np.linalg.norm(rg[s]), 1e-300)) for n, s in tensor_slices(dims)}
+    worst = max(per.items(), key=lambda kv: kv[1])
+    say(f"[gpu] {label}: bits rel {bits_err:.2e}, grad rel {err:.2e}, worst tensor {worst[0]} {worst[1]:.2e}")
+    assert bits_err <= BITS_TOL
+    assert err <= GRAD_TOL
+    for n, e in per.items():
+        assert e <= GRAD_TOL, (n, e)
+    # masked taps of the first kernel get no gradient
+    h, C, _, _ = dims
+    K = 2 * h + 1
+    m = torch_ref.causal_mask(h).numpy().astype(bool)
+    cw = gg[:C * 3 * K * K].reshape(C, 3, K, K)
+    assert np.all(cw[:, :, ~m] == 0.0)
+    return gg
+
+
+def test_grad_tiny_8x8(tr):
+    """Gradient check on the tiny model (8x8x3 images, h=3, C=8, one block)."""
+    say("[gpu] train: tiny model, 2 images 8x8")
+    _, blob = tr
+    dims, params = model("tiny", blob)
+    imgs = crops(2, 8, 7)
+    compare(dims, params, imgs, [1.0, 1.0], tr, "tiny 2x8x8")
+    # per-image weights of the loss
+    compare(dims, params, imgs, [0.25, -1.5], tr, "tiny weighted")
+
+
+def test_grad_tiny_edge_values(tr):
+    """Pixels at 0 and 255 (edge bins) and a ragged tile (W = 5)."""
+    say("[gpu] train: tiny model, edge values, 3 images 6x5")
+    _, blob = tr
+    dims, params = model("tiny", blob)
+    rng = np.random.default_rng(3)
+    imgs = rng.choice(np.array([0, 1, 2, 127, 128, 253, 254, 255], dtype=np.uint8), size=(3, 6, 5, 3))
+    compare(dims, params, imgs, [1.0, 2.0, 0.5], tr, "tiny edge values")
+
+
+@pytest.mark.parametrize("name", ["A", "C"])
+def test_grad_models_A_C(tr, name):
+    say(f"[gpu] train: model {name}, 8 crops 32x32")
+    _, blob = tr
+    dims, params = model(name, blob)
+    compare(dims, params, crops(8, 32, 11), np.ones(8), tr, f"model {name} 8x32x32")
+
+
+def test_grad_model_B_training_batch(tr):
+    """The training configuration: model B, 64 random 32x32 crops."""
+    say("[gpu] train: model B, 64 crops 32x32")
+    _, blob = tr
+    dims, params = model("B", blob)
+    compare(dims, params, crops(64, 32, 5_999_999), np.ones(64), tr, "model B 64x32x32")
+
+
+def test_backward_is_deterministic(tr):
+    say("[gpu] train: determinism")
+    train, blob = tr
+    dims, params = model("A", blob)
+    imgs = crops(16, 32, 1)
+    g1 = gpu_bits_grad(train, dims, params, imgs, np.ones(16))[1]
+    g2 = gpu_bits_grad(train, dims, params, imgs, np.ones(16))[1]
+    assert np.array_equal(g1, g2)
+
+
+def test_adam_lowers_bits(tr):
+    """A short run of Adam on the code length lowers bits/dim of held-out crops."""
+    say("[gpu] train: 60 Adam steps, model A")
+    train, blob = tr
+    dims, params = model("A", blob)
+    pool = synth.training_pool(n=64)
+    rng = np.random.Generator(np.random.PCG64(5_999_999))
+    held = torch.from_numpy(synth.training_crops(pool, 16, 32, np.random.default_rng(9))).cuda()
+    p = torch.nn.Parameter(torch.from_numpy(params).cuda())
+    opt = torch.optim.Adam([p], lr=1e-3)
+
+    def bpd():
+        with torch.no_grad():
+            return float(train.nll_bits(p, dims, held).sum()) / (held.numel())
+
+    before = bpd()
+    for _ in range(60):
+        x = torch.from_numpy(synth.training_crops(pool, 32, 32, rng)).cuda()
+        opt.zero_grad()
+        loss = train.nll_bits(p, dims, x).sum() / x.numel()
+        loss.backward()
+        opt.step()
+    after = bpd()
+    say(f"[gpu] bits/dim {before:.4f} -> {after:.4f}")
+    assert after < before - 0.5
