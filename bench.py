@@ -70,6 +70,8 @@ def main():
                     help="rows of the 1024-wide strip the raster baseline decodes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-lanes", type=int, default=48, help="64x64 lanes the oracle decodes")
+    ap.add_argument("--train-steps", type=int, default=50,
+                    help="timed training steps (model B, 64 random 32x32 crops, Adam); 0 skips the leg")
     ap.add_argument("--profile", action="store_true",
                     help="time only the batch decode, then run a known-size copy for counter calibration "
                          "(for profiler runs; prints no JSON line)")
@@ -236,6 +238,43 @@ def main():
                          f"FP64 C oracle, 1 thread, {cpu_s:.1f}s"}
         log(f"[bench] oracle CPU: {cpu['value']:.1f} px/s")
 
+    # training leg: one step = forward + hand-written backward + Adam on
+    # 64 random 32x32 crops, model B
+    train_rec = None
+    if args.train_steps > 0:
+        from paper_2201_05213_amd import blob as nxblob, train as nxtrain
+
+        tdims, tparams = nxblob.params_from_blob(blob)
+        pool = torch.from_numpy(synth.training_pool(n=512)).to(dev)
+        rng = np.random.Generator(np.random.PCG64(5_999_999))
+        p = torch.nn.Parameter(torch.from_numpy(tparams).to(dev))
+        opt = torch.optim.Adam([p], lr=1e-3)
+        batches = [nxtrain.random_crops(pool, 64, 32, rng) for _ in range(args.train_steps + 5)]
+
+        def train_step(x):
+            opt.zero_grad(set_to_none=True)
+            loss = nxtrain.nll_bits(p, tdims, x).sum() / x.numel()
+            loss.backward()
+            opt.step()
+
+        for x in batches[:5]:
+            train_step(x)
+        torch.cuda.synchronize()
+        ts0, ts1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts0.record(stream)
+        for x in batches[5:]:
+            train_step(x)
+        ts1.record(stream)
+        torch.cuda.synchronize()
+        tstep = ts0.elapsed_time(ts1) / 1e3 / args.train_steps
+        tpx = 64 * 32 * 32
+        # forward 1x, backward ~2x the forward's multiply-accumulates
+        tflops = 3 * flops_per_px * tpx / tstep
+        train_rec = {"step_ms": tstep * 1e3, "px_per_s": tpx / tstep, "tflops_fwd_bwd": tflops / 1e12,
+                     "frac_fp32_peak": tflops / PEAK_FP32,
+                     "sample": "model B, 64 random 32x32 crops per step, forward + backward + Adam"}
+        log(f"[bench] training step {tstep * 1e3:.3f} ms ({tflops / 1e12:.1f} TFLOP/s fwd+bwd)")
+
     out = {
         "metric": "decoded pixels/sec on 1 GPU, wavefront+patch vs raster; bits/dim gap vs FP64 oracle",
         "value": value,
@@ -269,6 +308,7 @@ def main():
                      "frac": achieved / PEAK_FP32, "flop_per_px": flops_per_px,
                      "traffic": decode_traffic_bytes(), "traffic_unit": "HBM bytes per launch"},
         "cpu_baseline": cpu,
+        "training": train_rec,
     }
     print(json.dumps(out))
 

@@ -20,7 +20,7 @@ import torch
 
 from ._lib import NelloxError, check, load
 
-__all__ = ["param_count", "nll_bits", "NLLFunction"]
+__all__ = ["param_count", "nll_bits", "NLLFunction", "random_crops", "bits_per_dim", "fit"]
 
 
 def _dims(dims) -> ctypes.Array:
@@ -84,3 +84,37 @@ class NLLFunction(torch.autograd.Function):
 def nll_bits(params: torch.Tensor, dims, imgs: torch.Tensor) -> torch.Tensor:
     """Code length in bits of each image (float64, shape (N,)); differentiable in params."""
     return NLLFunction.apply(params, dims, imgs)
+
+
+def random_crops(pool: torch.Tensor, batch: int, crop: int, rng) -> torch.Tensor:
+    """`batch` crop x crop windows of a (N, H, W, 3) uint8 GPU pool, at
+    positions drawn from the numpy Generator `rng` (image, row, column)."""
+    N, H, W, _ = pool.shape
+    ii = torch.from_numpy(rng.integers(0, N, size=batch)).to(pool.device)
+    yy = torch.from_numpy(rng.integers(0, H - crop + 1, size=batch)).to(pool.device)
+    xx = torch.from_numpy(rng.integers(0, W - crop + 1, size=batch)).to(pool.device)
+    ar = torch.arange(crop, device=pool.device)
+    return pool[ii[:, None, None], (yy[:, None] + ar)[:, :, None], (xx[:, None] + ar)[:, None, :]].contiguous()
+
+
+def bits_per_dim(params: torch.Tensor, dims, imgs: torch.Tensor) -> float:
+    with torch.no_grad():
+        return float(nll_bits(params, dims, imgs).sum()) / imgs.numel()
+
+
+def fit(params: torch.Tensor, dims, pool: torch.Tensor, steps: int, rng, batch: int = 64, crop: int = 32,
+        lr: float = 1e-3, on_step=None) -> torch.Tensor:
+    """Adam on bits/dim of random crops of `pool`; returns the trained
+    parameter vector (a new tensor). on_step(step, loss_tensor) is called
+    after every step if given."""
+    p = torch.nn.Parameter(params.detach().clone())
+    opt = torch.optim.Adam([p], lr=lr)
+    for step in range(steps):
+        x = random_crops(pool, batch, crop, rng)
+        opt.zero_grad(set_to_none=True)
+        loss = nll_bits(p, dims, x).sum() / x.numel()
+        loss.backward()
+        opt.step()
+        if on_step is not None:
+            on_step(step, loss)
+    return p.detach()

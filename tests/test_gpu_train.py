@@ -142,6 +142,23 @@ def test_backward_is_deterministic(tr):
     assert np.array_equal(g1, g2)
 
 
+def test_train_2000_adam_steps(tr):
+    """The training configuration end to end: model B, 2000 Adam steps at
+    lr 1e-3 on 64 random 32x32 crops per step from a pool of 512 synthetic
+    64x64 images; bits/dim of 64 held-out images must drop."""
+    say("[gpu] train: model B, 2000 Adam steps")
+    train, blob = tr
+    dims, params = model("B", blob)
+    pool = torch.from_numpy(synth.training_pool(n=512)).cuda()
+    held = torch.from_numpy(synth.training_pool(n=64, seed_base=5_500_000)).cuda()
+    p0 = torch.from_numpy(params).cuda()
+    before = train.bits_per_dim(p0, dims, held)
+    p = train.fit(p0, dims, pool, 2000, np.random.Generator(np.random.PCG64(5_999_999)))
+    after = train.bits_per_dim(p, dims, held)
+    say(f"[gpu] model B held-out bits/dim {before:.4f} -> {after:.4f} after 2000 steps")
+    assert np.isfinite(after) and after < before - 2.0
+
+
 def test_adam_lowers_bits(tr):
     """A short run of Adam on the code length lowers bits/dim of held-out crops."""
     say("[gpu] train: 60 Adam steps, model A")
