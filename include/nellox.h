@@ -15,7 +15,9 @@
  *   Probabilities are quantised to 16-bit CDFs
  *       cdf_k = k + floor(clamp(F(B_k), 0, 1) * 65280),  B_k = (2k - 256)/255,
  *   so every symbol has frequency >= 1 and the total is 2^16, and coded with
- *   byte-renormalising rANS (32-bit state, L = 2^23, start state 1).
+ *   byte-renormalising rANS (32-bit state, L = 2^23, start state 1), one
+ *   stream per lane or K = 2, 4 interleaved streams per lane (opts.interleave):
+ *   in a wavefront step, row i - i_first goes to stream (i - i_first) mod K.
  *   Decoding order (nellox_opts.order):
  *     0 raster: one pixel after the other (the sequential decoder of Sec. 2);
  *     1 wavefront: pixel (i,j) at step t = j + (h+1) i, all pixels of a step
@@ -63,10 +65,13 @@ typedef enum {
 } nellox_status;
 
 typedef struct {
-  int32_t order;   /* 0 raster, 1 wavefront */
-  int32_t patch_h; /* patch rows; <= 0 or >= H: whole image */
-  int32_t patch_w; /* patch columns; <= 0 or >= W: whole image */
-  int32_t reserved;
+  int32_t order;      /* 0 raster, 1 wavefront */
+  int32_t patch_h;    /* patch rows; <= 0 or >= H: whole image */
+  int32_t patch_w;    /* patch columns; <= 0 or >= W: whole image */
+  int32_t interleave; /* rANS states per lane: 0 or 1 = one; 2 or 4 (wavefront order
+                         only): the rows of every wavefront step are dealt to the
+                         states in turn, so a decoder can search that many symbols
+                         at once; each extra state costs one stream flush */
 } nellox_opts;
 
 typedef struct {

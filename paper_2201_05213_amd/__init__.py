@@ -23,9 +23,9 @@ RASTER = 0
 WAVEFRONT = 1
 
 
-def _opts(order: int, patch) -> NelloxOpts:
+def _opts(order: int, patch, interleave: int = 1) -> NelloxOpts:
     ph, pw = (0, 0) if patch is None else (int(patch[0]), int(patch[1]))
-    return NelloxOpts(int(order), ph, pw, 0)
+    return NelloxOpts(int(order), ph, pw, int(interleave))
 
 
 def _images(imgs: Sequence[torch.Tensor]):
@@ -78,20 +78,21 @@ class Model:
         return torch.empty(nb, dtype=torch.uint8, device=self.device)
 
     @staticmethod
-    def encode_bound(H: int, W: int, order: int = WAVEFRONT, patch=None) -> int:
-        o = _opts(order, patch)
+    def encode_bound(H: int, W: int, order: int = WAVEFRONT, patch=None, interleave: int = 1) -> int:
+        o = _opts(order, patch, interleave)
         return int(load().nellox_encode_bound(H, W, ctypes.byref(o)))
 
     # ------------------------------------------------------------------ coding
     def encode(self, imgs: Sequence[torch.Tensor], order: int = WAVEFRONT, patch=None, sync: bool = True,
-               ws: torch.Tensor | None = None):
+               ws: torch.Tensor | None = None, interleave: int = 1):
         """Returns (containers: uint8 CUDA tensor, offsets: int64 CUDA tensor
-        of n+1). With sync=True the container tensor is trimmed to its size."""
+        of n+1). With sync=True the container tensor is trimmed to its size.
+        interleave = rANS streams per lane (1, 2 or 4)."""
         L = load()
         n = len(imgs)
-        o = _opts(order, patch)
+        o = _opts(order, patch, interleave)
         arr = _images(imgs)
-        cap = sum(self.encode_bound(int(t.shape[0]), int(t.shape[1]), order, patch) for t in imgs)
+        cap = sum(self.encode_bound(int(t.shape[0]), int(t.shape[1]), order, patch, interleave) for t in imgs)
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=self.device)
         offs = torch.empty(n + 1, dtype=torch.int64, device=self.device)
         if ws is None:
@@ -105,12 +106,12 @@ class Model:
 
     def decode(self, data: torch.Tensor, offsets: torch.Tensor, shapes, order: int = WAVEFRONT, patch=None,
                out: Sequence[torch.Tensor] | None = None, sync: bool = True, trace: bool = False,
-               ws: torch.Tensor | None = None):
+               ws: torch.Tensor | None = None, interleave: int = 1):
         """Returns (images, status[, sym_dump]). With sync=True a non-OK
-        status raises NelloxError."""
+        status raises NelloxError. interleave must match the containers."""
         L = load()
         n = len(shapes)
-        o = _opts(order, patch)
+        o = _opts(order, patch, interleave)
         imgs = _shape_images(shapes, self.device) if out is None else list(out)
         arr = _images(imgs)
         status = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
@@ -179,11 +180,11 @@ class Model:
 
 
 def peek(container: bytes):
-    """(H, W, order, (patch_h, patch_w)) of a container held on the host."""
+    """(H, W, order, (patch_h, patch_w), interleave) of a container held on the host."""
     L = load()
     buf = ctypes.create_string_buffer(bytes(container[:64]), min(len(container), 64))
     H, W = ctypes.c_int32(), ctypes.c_int32()
     o = NelloxOpts()
     check(L.nellox_peek(buf, min(len(container), 64), ctypes.byref(H), ctypes.byref(W), ctypes.byref(o)),
           "nellox_peek")
-    return H.value, W.value, o.order, (o.patch_h, o.patch_w)
+    return H.value, W.value, o.order, (o.patch_h, o.patch_w), o.interleave

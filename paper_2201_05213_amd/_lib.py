@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnellox.so")
 
 class NelloxOpts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("patch_h", ctypes.c_int32), ("patch_w", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("interleave", ctypes.c_int32)]
 
 
 class NelloxImage(ctypes.Structure):

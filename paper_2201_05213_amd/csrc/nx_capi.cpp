@@ -99,6 +99,7 @@ hipError_t stage_copy(nellox_model* m, void* dst, const void* src, size_t bytes,
 struct Plan {
   std::vector<ImgDesc> d;
   int64_t n_tiles = 0, n_lanes = 0, n_px = 0, slot_bytes = 0;
+  int K = 1;  // rANS streams per lane
 };
 
 nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* o, Plan& P, bool need_px) {
@@ -106,6 +107,9 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
   if (n > 0 && !imgs) return fail(NELLOX_E_ARG, "imgs is null");
   if (!o) return fail(NELLOX_E_ARG, "opts is null");
   if (o->order != 0 && o->order != 1) return fail(NELLOX_E_ARG, "order must be 0 (raster) or 1 (wavefront)");
+  P.K = o->interleave <= 1 ? 1 : o->interleave;
+  if (!valid_interleave(P.K)) return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2 or 4");
+  if (P.K > 1 && o->order != 1) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
   P.d.resize(n);
   for (int k = 0; k < n; ++k) {
     const nellox_image& im = imgs[k];
@@ -130,7 +134,7 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     P.n_lanes += nl;
     P.n_px += npx;
     P.n_tiles += (int64_t)im.H * D.ntx;
-    P.slot_bytes += 6 * npx + 8 * nl;
+    P.slot_bytes += P.K * (6 * npx + 8 * nl);
   }
   return NELLOX_OK;
 }
@@ -145,8 +149,8 @@ WsLayout ws_layout(const Plan& P, int n) {
   W.desc = o; o = align256(o + (int64_t)sizeof(ImgDesc) * std::max(n, 1));
   W.flags = o; o = align256(o + 64);
   W.img_bytes = o; o = align256(o + 8LL * std::max(n, 1));
-  W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes, 1));
-  W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes, 1));
+  W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
+  W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
   W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
   W.sym = o; o = align256(o + 12 * std::max<int64_t>(P.n_px, 1));
   W.slots = o; o = align256(o + std::max<int64_t>(P.slot_bytes, 1));
@@ -373,9 +377,11 @@ size_t nellox_encode_bound(int32_t H, int32_t W, const nellox_opts* o) {
   if (H < 1 || W < 1) return 0;
   const int ph = (!o || o->patch_h <= 0 || o->patch_h > H) ? H : o->patch_h;
   const int pw = (!o || o->patch_w <= 0 || o->patch_w > W) ? W : o->patch_w;
+  const int64_t K = (!o || o->interleave <= 1) ? 1 : o->interleave;
+  if (!valid_interleave((int)K)) return 0;
   const int64_t nl = (int64_t)((H + ph - 1) / ph) * ((W + pw - 1) / pw);
-  // header, lane table, per lane 4 flush bytes, at most 2 bytes per symbol
-  return (size_t)(HDR_BYTES + 4 * nl + 4 * nl + 6LL * H * W);
+  // header, stream table, per stream 4 flush bytes, at most 2 bytes per symbol
+  return (size_t)(HDR_BYTES + 4 * nl * K + 4 * nl * K + 6LL * H * W);
 }
 
 size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* o) {
@@ -409,6 +415,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   r.n_lanes = P.n_lanes;
   r.order = o->order;
   r.h = m->h;
+  r.K = P.K;
   r.sym = (const uint32_t*)(w8 + W.sym);
   r.slots = w8 + W.slots;
   r.lane_len = (uint32_t*)(w8 + W.lane_len);
@@ -420,6 +427,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   pk.n_lanes = P.n_lanes;
   pk.order = o->order;
   pk.h = m->h;
+  pk.K = P.K;
   pk.model_hash = m->hash;
   pk.slots = w8 + W.slots;
   pk.lane_len = r.lane_len;
@@ -438,7 +446,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
 
 nellox_status nellox_peek(const uint8_t* c, size_t len, int32_t* H, int32_t* W, nellox_opts* o) {
   if (!c) return fail(NELLOX_E_ARG, "container is null");
-  if (len < (size_t)HDR_BYTES || memcmp(c, "NLXC", 4) != 0 || c[4] != CONTAINER_VERSION || c[7] != CODER_RANS8)
+  if (len < (size_t)HDR_BYTES || memcmp(c, "NLXC", 4) != 0 || c[4] != CONTAINER_VERSION || !valid_interleave(c[7]))
     return fail(NELLOX_E_CORRUPT, "not a container of this version");
   const int32_t h = (int32_t)rd32(c + 8), w = (int32_t)rd32(c + 12);
   if (H) *H = h;
@@ -447,7 +455,7 @@ nellox_status nellox_peek(const uint8_t* c, size_t len, int32_t* H, int32_t* W, 
     o->order = c[5];
     o->patch_h = c[16] | (c[17] << 8);
     o->patch_w = c[18] | (c[19] << 8);
-    o->reserved = 0;
+    o->interleave = c[7];
   }
   return NELLOX_OK;
 }
@@ -478,16 +486,20 @@ static nellox_status decode_impl(const nellox_model* mc, int32_t n, const uint8_
   a.n_img = n;
   a.n_lanes = P.n_lanes;
   a.order = o->order;
+  a.K = P.K;
   a.model_hash = m->hash;
   a.in = in;
   a.in_off = in_offsets;
   a.status = status;
   a.counter = counter;
   a.sym_dump = dump;
-  int grid = persistent_grid(m);
-  const int64_t need = (P.n_lanes + DECODE_WAVES - 1) / DECODE_WAVES;
-  if (need < grid) grid = (int)std::max<int64_t>(need, 1);
-  e = launch_decode(m->h, m->Cp, a, grid, s);
+  // spread the lanes over every CU: waves per workgroup = lanes per CU
+  // (at most DECODE_WAVES), one workgroup per CU while lanes remain; the
+  // waves of a CU share its LDS (weights, pivot tables, cross-lane traffic)
+  const int cus = persistent_grid(m);
+  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
+  const int grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
+  e = launch_decode(m->h, m->Cp, a, grid, waves, s);
   if (e != hipSuccess) return hip_fail(e, "decoder launch");
   return NELLOX_OK;
 }

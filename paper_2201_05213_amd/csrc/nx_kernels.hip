@@ -12,6 +12,7 @@
 
 #include "nx_device.hpp"
 #include "nx_kernels.hpp"
+#include "nx_order.hpp"
 
 namespace nx {
 
@@ -76,17 +77,10 @@ NXD ImgDesc uniform_desc(const ImgDesc* __restrict__ p) {
 
 NXD uint32_t uniform_u(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
-// rows active at wavefront step t of an Hl x Wl lane, step offset o = h + 1
-NXD void step_rows(int t, int Hl, int Wl, int o, int& ilo, int& ihi) {
-  const int a = t - (Wl - 1);
-  ilo = a <= 0 ? 0 : (a + o - 1) / o;
-  ihi = min(Hl - 1, t / o);
-}
-
-template <int NT>
+// the whole workgroup (any block size) copies the weight image into LDS
 NXD void load_weights(float* lds, const float* __restrict__ w, int64_t nfloats) {
   const int64_t n4 = nfloats >> 2;
-  for (int64_t i = threadIdx.x; i < n4; i += NT) ((float4*)lds)[i] = ((const float4*)w)[i];
+  for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) ((float4*)lds)[i] = ((const float4*)w)[i];
   __syncthreads();
 }
 
@@ -95,7 +89,7 @@ template <int H_, int C_>
 __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
-  load_weights<NWAVES * 64>(w, A.w, A.wfloats);
+  load_weights(w, A.w, A.wfloats);
   const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
   const int64_t gw = (int64_t)blockIdx.x * NWAVES + (threadIdx.x >> 6);
@@ -159,59 +153,12 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
 }
 
 // ------------------------------------------------------------------ rANS encoder
-// Symbols of a lane in decode order:
-//   wavefront: steps t ascending; within a step the active rows are cut into
-//   groups of 16 consecutive rows; per group channels R, G, B; per channel
-//   rows ascending.
-//   raster: rows, columns, channels.
-// The encoder walks this order backwards.
-struct RevOrder {
-  int Hl, Wl, o, raster;
-  int t, ilo, ihi, ts, te, c, i, j;
-  bool done;
-
-  // enter step t, or the closest earlier non-empty one: a lane narrower than
-  // h + 1 columns has steps without any pixel (step 0 is never empty)
-  NXD void set_step() {
-    for (;;) {
-      step_rows(t, Hl, Wl, o, ilo, ihi);
-      if (ilo <= ihi) break;
-      if (--t < 0) { done = true; return; }
-    }
-    ts = ilo + ((ihi - ilo) / 16) * 16;
-    te = min(ts + 15, ihi);
-    c = 2;
-    i = te;
-  }
-  NXD void init(int Hl_, int Wl_, int o_, int raster_) {
-    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; done = false;
-    if (raster) { i = Hl - 1; j = Wl - 1; c = 2; }
-    else { t = Wl + o * (Hl - 1) - 1; set_step(); }
-  }
-  // current symbol: row i, column col(), channel c
-  NXD int col() const { return raster ? j : t - o * i; }
-  NXD void advance() {
-    if (raster) {
-      if (--c >= 0) return;
-      c = 2;
-      if (--j >= 0) return;
-      j = Wl - 1;
-      if (--i >= 0) return;
-      done = true;
-      return;
-    }
-    if (--i >= ts) return;
-    if (--c >= 0) { i = te; return; }
-    ts -= 16;
-    if (ts >= ilo) { te = ts + 15; c = 2; i = te; return; }
-    if (--t < 0) { done = true; return; }
-    set_step();
-  }
-};
-
+// one thread per stream (lane L, stream k): stream index L K + k
 __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
-  const int64_t L = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (L >= A.n_lanes) return;
+  const int64_t SL = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (SL >= A.n_lanes * A.K) return;
+  const int64_t L = SL / A.K;
+  const int kk = (int)(SL - L * A.K);
   const int n = find_img(A.desc, A.n_img, L, true);
   const ImgDesc D = A.desc[n];
   const int q = (int)(L - D.lane_base);
@@ -219,11 +166,12 @@ __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
   const int y0 = ly * D.ph, x0 = lx * D.pw;
   const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
   const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
-  const int64_t slot_end = D.slot_base + 6 * lane_px_off + 8 * (int64_t)q + lane_slot_bytes((int64_t)Hl * Wl);
+  const int64_t slot_end = D.slot_base + A.K * (6 * lane_px_off + 8 * (int64_t)q) +
+                           (kk + 1) * lane_slot_bytes((int64_t)Hl * Wl);
   uint8_t* out = A.slots + slot_end;
   const uint32_t* sym = A.sym + D.px_base * 3;
   RevOrder it;
-  it.init(Hl, Wl, A.h + 1, A.order == 0);
+  it.init(Hl, Wl, A.h + 1, A.order == 0, A.K, kk);
   uint32_t x = RANS_X0;
   constexpr int B = 16;  // symbols fetched per batch (independent loads in flight)
   while (!it.done) {
@@ -253,7 +201,7 @@ __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
   out[1] = (uint8_t)(x >> 8);
   out[2] = (uint8_t)(x >> 16);
   out[3] = (uint8_t)(x >> 24);
-  A.lane_len[L] = (uint32_t)((A.slots + slot_end) - out);
+  A.lane_len[SL] = (uint32_t)((A.slots + slot_end) - out);
 }
 
 // ------------------------------------------------------------------ container assembly
@@ -263,12 +211,13 @@ __global__ void __launch_bounds__(256) k_lane_scan(PackArgs A) {
   __shared__ uint32_t carry;
   const int n = blockIdx.x;
   const ImgDesc D = A.desc[n];
-  const int nl = D.nlx * D.nly;
+  const int nl = D.nlx * D.nly * A.K;  // streams of this image
+  const int64_t sbase = D.lane_base * A.K;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int b0 = 0; b0 < nl; b0 += 256) {
     const int q = b0 + threadIdx.x;
-    const uint32_t v = q < nl ? A.lane_len[D.lane_base + q] : 0u;
+    const uint32_t v = q < nl ? A.lane_len[sbase + q] : 0u;
     part[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
@@ -277,12 +226,12 @@ __global__ void __launch_bounds__(256) k_lane_scan(PackArgs A) {
       part[threadIdx.x] += add;
       __syncthreads();
     }
-    if (q < nl) A.lane_end[D.lane_base + q] = carry + part[threadIdx.x];
+    if (q < nl) A.lane_end[sbase + q] = carry + part[threadIdx.x];
     __syncthreads();
     if (threadIdx.x == 255) carry += part[255];
     __syncthreads();
   }
-  if (threadIdx.x == 0) A.img_bytes[n] = (uint64_t)HDR_BYTES + 4ull * nl + carry;
+  if (threadIdx.x == 0) A.img_bytes[n] = (uint64_t)HDR_BYTES + 4ull * nl + carry;  // nl = streams
 }
 
 __global__ void k_img_scan(PackArgs A) {
@@ -296,35 +245,38 @@ __global__ void k_img_scan(PackArgs A) {
   *A.overflow = acc > A.out_cap ? 1 : 0;
 }
 
-// one 64-thread block per lane: payload copy, lane table entry, header
+// one 64-thread block per stream: payload copy, stream table entry, header
 __global__ void __launch_bounds__(64) k_pack(PackArgs A) {
   if (*A.overflow) return;
-  const int64_t L = blockIdx.x;
+  const int64_t SL = blockIdx.x;
+  const int64_t L = SL / A.K;
+  const int kk = (int)(SL - L * A.K);
   const int n = find_img(A.desc, A.n_img, L, true);
   const ImgDesc D = A.desc[n];
   const int q = (int)(L - D.lane_base);
   const int nl = D.nlx * D.nly;
   const int ly = q / D.nlx, lx = q - ly * D.nlx;
-  const int y0 = ly * D.ph, x0 = lx * D.pw;
-  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
-  (void)x0;
+  const int y0 = ly * D.ph;
+  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - lx * D.pw);
   const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
-  const int64_t slot_end = D.slot_base + 6 * lane_px_off + 8 * (int64_t)q + lane_slot_bytes((int64_t)Hl * Wl);
-  const uint32_t len = A.lane_len[L];
-  const uint32_t end = A.lane_end[L];
+  const int64_t slot_end = D.slot_base + A.K * (6 * lane_px_off + 8 * (int64_t)q) +
+                           (kk + 1) * lane_slot_bytes((int64_t)Hl * Wl);
+  const uint32_t len = A.lane_len[SL];
+  const uint32_t end = A.lane_end[SL];
+  const int64_t entry = (int64_t)q * A.K + kk;
   uint8_t* C = A.out + A.out_offsets[n];
-  uint8_t* dst = C + HDR_BYTES + 4 * (int64_t)nl + (end - len);
+  uint8_t* dst = C + HDR_BYTES + 4 * (int64_t)nl * A.K + (end - len);
   const uint8_t* src = A.slots + slot_end - len;
   for (uint32_t k = threadIdx.x; k < len; k += 64) dst[k] = src[k];
-  if (threadIdx.x < 4) C[HDR_BYTES + 4 * (int64_t)q + threadIdx.x] = (uint8_t)(end >> (8 * threadIdx.x));
-  if (q == 0 && threadIdx.x == 0) {
+  if (threadIdx.x < 4) C[HDR_BYTES + 4 * entry + threadIdx.x] = (uint8_t)(end >> (8 * threadIdx.x));
+  if (entry == 0 && threadIdx.x == 0) {
     uint8_t h[HDR_BYTES];
     for (int k = 0; k < HDR_BYTES; ++k) h[k] = 0;
     h[0] = 'N'; h[1] = 'L'; h[2] = 'X'; h[3] = 'C';
     h[4] = CONTAINER_VERSION;
     h[5] = (uint8_t)A.order;
     h[6] = (uint8_t)A.h;
-    h[7] = CODER_RANS8;
+    h[7] = (uint8_t)A.K;
     for (int k = 0; k < 4; ++k) h[8 + k] = (uint8_t)((uint32_t)D.H >> (8 * k));
     for (int k = 0; k < 4; ++k) h[12 + k] = (uint8_t)((uint32_t)D.W >> (8 * k));
     const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
@@ -341,30 +293,50 @@ __global__ void __launch_bounds__(64) k_pack(PackArgs A) {
 // bytes base + 4l .. base + 4l + 3; a byte is fetched with a lane read.
 struct ByteStage {
   const uint8_t* S;
-  int64_t len, base;
+  uint32_t len, base;
   uint32_t word;
-  NXD void fill(int64_t at, int lane) {
+  NXD void fill(uint32_t at, int lane) {
     // clamped, unconditional loads; bytes past the end read as 0
     base = at;
     const gbytes g = as_global(S);
     uint32_t v = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int64_t o = at + 4 * lane + b;
+      const uint32_t o = at + 4 * (uint32_t)lane + b;
       const uint32_t byte = g[o < len ? o : len - 1];
       v |= (o < len ? byte : 0u) << (8 * b);
     }
     word = v;
   }
-  NXD uint32_t get(int64_t pos, int lane) {
-    if (pos - base >= 256) fill(pos, lane);
-    const int off = (int)(pos - base);
-    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)word, off >> 2);
-    return (v >> (8 * (off & 3))) & 255u;
+  // byte at pos, pos >= base; the caller keeps pos < base + 256 (bytes past
+  // the window read as garbage, never as an out-of-range lane)
+  NXD uint32_t byte_at(uint32_t pos) const {
+    const uint32_t off = pos - base;
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)word, (int)((off >> 2) & 63u));
+    return (v >> (8 * (off & 3u))) & 255u;
+  }
+  NXD uint32_t get(uint32_t pos, int lane) {
+    if (pos - base >= 256u) fill(pos, lane);
+    return byte_at(pos);
+  }
+  // rANS renormalisation after a pop: at most two bytes are read (the popped
+  // state is at least 2^7 while bytes remain), each only while x < L and
+  // bytes remain; no branch except the rare window refill
+  NXD void renorm(uint32_t& x, uint32_t& pos, int lane, bool act = true) {
+    if (pos + 2u > base + 256u && pos < len) fill(pos & ~3u, lane);
+    const uint32_t b0 = byte_at(pos), b1 = byte_at(pos + 1u);
+    const bool r0 = act && x < RANS_L && pos < len;
+    x = r0 ? ((x << 8) | b0) : x;
+    pos += r0 ? 1u : 0u;
+    const bool r1 = x < RANS_L && pos < len;
+    x = r1 ? ((x << 8) | b1) : x;
+    pos += r1 ? 1u : 0u;
   }
 };
 
-template <int H_, int C_>
+// K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
+// streams k) per iteration, their searches independent of each other.
+template <int H_, int C_, bool TRACE, int K>
 __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int64_t L, int lane) {
   const int p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
@@ -377,15 +349,15 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
   const uint8_t* C = A.in + uniform64((int64_t)A.in_off[n]);
   const int64_t clen = uniform64((int64_t)(A.in_off[n + 1] - A.in_off[n]));
-  const int64_t pay = HDR_BYTES + 4 * (int64_t)nl;
-  // header and lane table checks (every lane reads the same bytes; the
+  const int64_t pay = HDR_BYTES + 4 * (int64_t)nl * K;
+  // header and stream table checks (every lane reads the same bytes; the
   // verdicts are made wave-uniform, and status is stored by every lane)
   bool ok = clen >= pay;
   bool mismatch = false;
   if (ok) {
     const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
     ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION &&
-         C[5] == (uint8_t)A.order && C[6] == (uint8_t)H_ && C[7] == CODER_RANS8 && rd_u32(C + 8) == (uint32_t)D.H &&
+         C[5] == (uint8_t)A.order && C[6] == (uint8_t)H_ && C[7] == (uint8_t)K && rd_u32(C + 8) == (uint32_t)D.H &&
          rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
          (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
     ok = uniform(ok ? 1 : 0) != 0;
@@ -398,27 +370,35 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     A.status[n] = ST_MISMATCH;
     return;
   }
-  uint32_t lend = 0, lstart = 0;
-  if (ok) {
-    lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (int64_t)q));
-    lstart = q > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (int64_t)(q - 1))) : 0u;
-    ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+  ByteStage R[K];
+  uint32_t x[K], pos[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t e = (int64_t)q * K + k;  // stream table entry
+    uint32_t lend = 0, lstart = 0;
+    if (ok) {
+      lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * e));
+      lstart = e > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (e - 1))) : 0u;
+      ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+    }
+    R[k].S = C + pay + lstart;
+    R[k].len = lend - lstart;
   }
   if (!ok) {
     A.status[n] = ST_CORRUPT;
     return;
   }
-  ByteStage R;
-  R.S = C + pay + lstart;
-  R.len = (int64_t)(lend - lstart);
-  R.fill(0, lane);
-  uint32_t x = R.get(0, lane) | (R.get(1, lane) << 8) | (R.get(2, lane) << 16) | (R.get(3, lane) << 24);
-  int64_t pos = 4;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    R[k].fill(0, lane);
+    x[k] = R[k].byte_at(0) | (R[k].byte_at(1) << 8) | (R[k].byte_at(2) << 16) | (R[k].byte_at(3) << 24);
+    pos[k] = 4;
+  }
   uint8_t* img = D.px;
   const int o = H_ + 1;
   const bool raster = A.order == 0;
   const int64_t ngroups = raster ? (int64_t)Hl * Wl : (int64_t)Wl + (int64_t)o * (Hl - 1);
-  uint32_t* dump = A.sym_dump ? A.sym_dump + D.px_base * 3 : nullptr;
+  uint32_t* dump = TRACE ? A.sym_dump + D.px_base * 3 : nullptr;
   TapCodes<H_> tc;
   tc.init(g);
 
@@ -445,88 +425,104 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       float xr = 0.0f, xg = 0.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Chan K;
-        chan_params(M, c, xr, xg, K);
+        Chan Q;
+        chan_params(M, c, xr, xg, Q);
         // pivot CDF values of every pixel of the group: cdf at k = 16 (j + 1),
         // j = 0..14, and 2^16 for k = 256 (independent evaluations)
 #pragma unroll 5
         for (int jp = 0; jp < 15; ++jp) {
-          const uint32_t v = cdf_quant(16 * (jp + 1), cdf_eval(16 * (jp + 1), K.w, K.a, K.b));
+          const uint32_t v = cdf_quant(16 * (jp + 1), cdf_eval(16 * (jp + 1), Q.w, Q.a, Q.b));
           if (g == 0) piv[p * 16 + jp] = v;
         }
         if (g == 0) piv[p * 16 + 15] = CDF_TOTAL;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // serial pops; the next pixel's pivot row and mixture (which do not
-        // depend on the coder state) are fetched one symbol ahead
-        float nw[3], nA[3], nB[3];
-        uint32_t npv = 0;
-        {
-          const int src = g << 4;
+        // pops, K per iteration (one per stream); the next iteration's pivot
+        // rows and mixtures (which do not depend on the coder states) are
+        // fetched one iteration ahead; rows past the group are clamped and
+        // their results unused
+        float nw[K][3], nA[K][3], nB[K][3];
+        uint32_t npv[K];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            nw[k] = __shfl(K.w[k], src);
-            nA[k] = __shfl(K.a[k], src);
-            nB[k] = __shfl(K.b[k], src);
+        for (int k = 0; k < K; ++k) {
+          const int src = (g << 4) | k;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            nw[k][j] = __shfl(Q.w[j], src);
+            nA[k][j] = __shfl(Q.a[j], src);
+            nB[k][j] = __shfl(Q.b[j], src);
           }
-          npv = piv[p];
+          npv[k] = piv[k * 16 + p];
         }
-        for (int pp = 0; pp < na; ++pp) {
-          float bw[3], bA[3], bB[3];
+        for (int q0 = 0; q0 < na; q0 += K) {
+          float bw[K][3], bA[K][3], bB[K][3];
+          uint32_t pv[K];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            bw[k] = nw[k];
-            bA[k] = nA[k];
-            bB[k] = nB[k];
-          }
-          const uint32_t pv = npv;
-          if (pp + 1 < na) {
-            const int src = (g << 4) | (pp + 1);
+          for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              nw[k] = __shfl(K.w[k], src);
-              nA[k] = __shfl(K.a[k], src);
-              nB[k] = __shfl(K.b[k], src);
+            for (int j = 0; j < 3; ++j) {
+              bw[k][j] = nw[k][j];
+              bA[k][j] = nA[k][j];
+              bB[k][j] = nB[k][j];
             }
-            npv = piv[(pp + 1) * 16 + p];
+            pv[k] = npv[k];
+            const int nx = min(q0 + K + k, 15);
+            const int src = (g << 4) | nx;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              nw[k][j] = __shfl(Q.w[j], src);
+              nA[k][j] = __shfl(Q.a[j], src);
+              nB[k][j] = __shfl(Q.b[j], src);
+            }
+            npv[k] = piv[nx * 16 + p];
           }
-          const uint32_t slot = x & 0xffffu;
-          // bucket: pivots of pixel pp at or below the slot (pv of lane p =
-          // cdf at 16 (p + 1); lane 15 holds 2^16)
-          const int b = __popcll(__ballot(pv <= slot) & 0xffffull);
-          // inside the bucket: cdf at k = 16 b + p for p = 1..15; the bucket's
-          // lower bound (p = 0) is cdf at 16 b <= slot by construction
-          const int k2 = 16 * b + p;
-          const uint32_t c2 = cdf_quant(k2, cdf_eval(max(k2, 1), bw, bA, bB));
-          const int cnt = __popcll(__ballot(c2 <= slot) & 0xfffeull);
-          const int s = 16 * b + cnt;
-          const uint32_t lo = b == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)pv, b - 1);
-          const uint32_t start = cnt == 0 ? lo : (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
-          const uint32_t next = cnt < 15 ? (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt + 1)
-                                         : (uint32_t)__builtin_amdgcn_readlane((int)pv, b);
-          const uint32_t freq = next - start;
-          x = freq * (x >> 16) + slot - start;
-          while (x < RANS_L && pos < R.len) {
-            x = (x << 8) | R.get(pos, lane);
-            ++pos;
+          uint32_t slot[K], start[K], freq[K];
+          int sym[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            slot[k] = x[k] & 0xffffu;
+            // bucket: pivots of the pixel at or below the slot (pv of lane p =
+            // cdf at 16 (p + 1); lane 15 holds 2^16, so b <= 15)
+            const int b = __popcll(__ballot(pv[k] <= slot[k]) & 0xffffull);
+            // inside the bucket: cdf at k = 16 b + p for p = 1..15; the
+            // bucket's lower bound (p = 0) is cdf at 16 b <= slot
+            const int k2 = 16 * b + p;
+            const uint32_t c2 = cdf_quant(k2, cdf_eval(max(k2, 1), bw[k], bA[k], bB[k]));
+            const int cnt = __popcll(__ballot(c2 <= slot[k]) & 0xfffeull);
+            sym[k] = 16 * b + cnt;
+            // bounds of the symbol, every read unconditional (no branches)
+            const uint32_t lo_r = (uint32_t)__builtin_amdgcn_readlane((int)pv[k], (b + 15) & 15);
+            const uint32_t st_r = (uint32_t)__builtin_amdgcn_readlane((int)c2, cnt);
+            const uint32_t nc_r = (uint32_t)__builtin_amdgcn_readlane((int)c2, (cnt + 1) & 15);
+            const uint32_t np_r = (uint32_t)__builtin_amdgcn_readlane((int)pv[k], b);
+            const uint32_t lo = b == 0 ? 0u : lo_r;
+            start[k] = cnt == 0 ? lo : st_r;
+            freq[k] = (cnt < 15 ? nc_r : np_r) - start[k];
           }
-          if (p == pp) {
-            if (c == 0) xv[0] = s;
-            else if (c == 1) xv[1] = s;
-            else xv[2] = s;
-          }
-          if (dump) {  // every lane stores the same value
-            const int ii = ts + pp;
-            const int jj = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * ii;
-            dump[((int64_t)(y0 + ii) * D.W + (x0 + jj)) * 3 + c] = start | (freq << 16);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const bool act = q0 + k < na;
+            const uint32_t xn = freq[k] * (x[k] >> 16) + slot[k] - start[k];
+            x[k] = act ? xn : x[k];
+            R[k].renorm(x[k], pos[k], lane, act);
+            if (p == q0 + k) {
+              if (c == 0) xv[0] = sym[k];
+              else if (c == 1) xv[1] = sym[k];
+              else xv[2] = sym[k];
+            }
+            if (TRACE && act) {  // every lane stores the same value
+              const int ii = ts + q0 + k;
+              const int jj = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * ii;
+              dump[((int64_t)(y0 + ii) * D.W + (x0 + jj)) * 3 + c] = start[k] | (freq[k] << 16);
+            }
           }
         }
         if (c == 0) {
-          posterior(M, xv[0], K.mu, K.is, has2);
+          posterior(M, xv[0], Q.mu, Q.is, has2);
           xr = normalise(xv[0]);
         } else if (c == 1) {
-          posterior(M, xv[1], K.mu, K.is, has2);
+          posterior(M, xv[1], Q.mu, Q.is, has2);
           xg = normalise(xv[1]);
         }
       }
@@ -540,15 +536,17 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       __threadfence_block();
     }
   }
-  const bool clean = x == RANS_X0 && pos == R.len;
+  bool clean = true;
+#pragma unroll
+  for (int k = 0; k < K; ++k) clean = clean && x[k] == RANS_X0 && pos[k] == R[k].len;
   if (!clean) A.status[n] = ST_CORRUPT;
 }
 
-template <int H_, int C_>
+template <int H_, int C_, bool TRACE, int K>
 __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
-  load_weights<NWAVES_DEC * 64>(w, A.w, A.wfloats);
+  load_weights(w, A.w, A.wfloats);
   const int lane = threadIdx.x & 63;
   uint32_t* piv = (uint32_t*)(w + A.wfloats) + (threadIdx.x >> 6) * PIV_WORDS;
   for (;;) {
@@ -558,7 +556,7 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
     if (lane == leader) L = atomicAdd(A.counter, 1);
     L = uniform(L);
     if ((int64_t)L >= A.n_lanes) break;
-    decode_lane<H_, C_>(A, w, piv, L, lane);
+    decode_lane<H_, C_, TRACE, K>(A, w, piv, L, lane);
   }
 }
 
@@ -606,13 +604,25 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int H_, int C_>
-static hipError_t decode_t(const DecArgs& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.wfloats * 4 + (size_t)NWAVES_DEC * PIV_WORDS * 4;
-  hipError_t e = allow_lds(k_decode<H_, C_>, lds);
+template <int H_, int C_, bool TRACE, int K>
+static hipError_t decode_tt(const DecArgs& a, int grid, int waves, hipStream_t s) {
+  const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * PIV_WORDS * 4;
+  hipError_t e = allow_lds(k_decode<H_, C_, TRACE, K>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode<H_, C_>), dim3(grid), dim3(NWAVES_DEC * 64), lds, s, a);
+  hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K>), dim3(grid), dim3(waves * 64), lds, s, a);
   return hipGetLastError();
+}
+
+template <int H_, int C_, int K>
+static hipError_t decode_k(const DecArgs& a, int grid, int waves, hipStream_t s) {
+  return a.sym_dump ? decode_tt<H_, C_, true, K>(a, grid, waves, s) : decode_tt<H_, C_, false, K>(a, grid, waves, s);
+}
+
+template <int H_, int C_>
+static hipError_t decode_t(const DecArgs& a, int grid, int waves, hipStream_t s) {
+  if (a.K == 2) return decode_k<H_, C_, 2>(a, grid, waves, s);
+  if (a.K == 4) return decode_k<H_, C_, 4>(a, grid, waves, s);
+  return decode_k<H_, C_, 1>(a, grid, waves, s);
 }
 
 #define NX_DISPATCH(FN, h, C, ...)                          \
@@ -633,14 +643,15 @@ hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s)
   NX_DISPATCH(pass_t, h, C, a, grid, s);
 }
 
-hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, hipStream_t s) {
+hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
-  NX_DISPATCH(decode_t, h, C, a, grid, s);
+  if (waves < 1 || waves > NWAVES_DEC) return hipErrorInvalidValue;
+  NX_DISPATCH(decode_t, h, C, a, grid, waves, s);
 }
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
-  const int grid = (int)((a.n_lanes + 63) / 64);
+  const int grid = (int)((a.n_lanes * a.K + 63) / 64);
   hipLaunchKernelGGL(k_rans_enc, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
@@ -648,7 +659,7 @@ hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_lane_scan, dim3(a.n_img), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_img_scan, dim3(1), dim3(64), 0, s, a);
-  if (a.n_lanes > 0) hipLaunchKernelGGL(k_pack, dim3((unsigned)a.n_lanes), dim3(64), 0, s, a);
+  if (a.n_lanes > 0) hipLaunchKernelGGL(k_pack, dim3((unsigned)(a.n_lanes * a.K)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

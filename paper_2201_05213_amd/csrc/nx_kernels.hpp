@@ -33,6 +33,7 @@ struct RansEncArgs {
   int64_t n_lanes;
   int order;               // 0 raster, 1 wavefront
   int h;
+  int K;                   // rANS streams per lane
   const uint32_t* sym;
   uint8_t* slots;
   uint32_t* lane_len;
@@ -43,10 +44,11 @@ struct PackArgs {
   int n_img;
   int64_t n_lanes;
   int order, h;
+  int K;                   // rANS streams per lane (entries of the stream table per lane)
   uint64_t model_hash;
   const uint8_t* slots;
-  const uint32_t* lane_len;
-  uint32_t* lane_end;      // scratch: cumulative payload bytes per lane
+  const uint32_t* lane_len;  // per stream (lane q K + k)
+  uint32_t* lane_end;      // scratch: cumulative payload bytes per stream
   uint64_t* img_bytes;     // scratch: container bytes per image
   uint8_t* out;
   uint64_t* out_offsets;   // n_img + 1
@@ -62,6 +64,7 @@ struct DecArgs {
   int n_img;
   int64_t n_lanes;
   int order;
+  int K;                   // rANS streams per lane
   uint64_t model_hash;
   const uint8_t* in;
   const uint64_t* in_off;  // n_img + 1
@@ -121,7 +124,8 @@ hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s)
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s);
-hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, hipStream_t s);
+// waves per workgroup in 1..DECODE_WAVES (the LDS takes one pivot table per wave)
+hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s);
 hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s);
 
 constexpr int TRAIN_BLOCK = 16 * 64;  // threads per workgroup of the per-tile training kernels

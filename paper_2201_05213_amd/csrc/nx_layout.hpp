@@ -63,12 +63,18 @@ struct ImgDesc {
 };
 static_assert(sizeof(ImgDesc) == 72, "descriptor layout");
 
-// Container header (little endian), followed by u32 lane_end[n_lanes]
-// (cumulative payload bytes per lane) and the lane payloads.
+// Container header (little endian), followed by u32 end[n_lanes * K]
+// (cumulative payload bytes per stream, stream k of lane q at q K + k) and
+// the stream payloads (4 final-state bytes, then the renormalisation bytes in
+// the order the decoder reads them).
 constexpr int HDR_BYTES = 32;
 constexpr uint8_t CONTAINER_VERSION = 1;
-constexpr uint8_t CODER_RANS8 = 1;  // byte-renormalising rANS, L=2^23, M=2^16, x0=1
-//  0 "NLXC" | 4 u8 version | 5 u8 order | 6 u8 h | 7 u8 coder | 8 u32 H | 12 u32 W
+// coder byte = K, the rANS streams per lane: byte-renormalising rANS,
+// L = 2^23, M = 2^16, start state 1, K in {1, 2, 4}
+constexpr uint8_t CODER_RANS8 = 1;
+constexpr int MAX_INTERLEAVE = 4;
+NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4; }
+//  0 "NLXC" | 4 u8 version | 5 u8 order | 6 u8 h | 7 u8 K | 8 u32 H | 12 u32 W
 // 16 u16 patch_h (0 = whole) | 18 u16 patch_w (0 = whole) | 20 u64 model hash
 // 28 u32 n_lanes
 

@@ -50,6 +50,9 @@ def test_host_only_calls(lib):
     # header + lane table + 4 flush bytes per lane + 2 bytes per symbol
     assert L.nellox_encode_bound(128, 128, ctypes.byref(o)) == 32 + 4 * 4 + 4 * 4 + 6 * 128 * 128
     assert L.nellox_encode_bound(0, 5, ctypes.byref(o)) == 0
+    o2 = _lib.NelloxOpts(1, 64, 64, 2)
+    assert L.nellox_encode_bound(128, 128, ctypes.byref(o2)) == 32 + 4 * 4 * 2 + 4 * 4 * 2 + 6 * 128 * 128
+    assert L.nellox_encode_bound(128, 128, ctypes.byref(_lib.NelloxOpts(1, 64, 64, 3))) == 0
     # bad blobs are rejected before any device call
     h = ctypes.c_void_p()
     assert L.nellox_model_create(b"NLXWxxxx", 8, ctypes.byref(h)) == 2

@@ -1,0 +1,115 @@
+"""CPU check of the coding order shared by the encoder and the decoder.
+
+The wavefront decoder (Sec. 3, Algorithm 1) pops a lane's symbols in this
+order: steps t ascending; the active rows of a step cut into groups of 16
+consecutive rows; per group the channels R, G, B; per channel the rows
+ascending, dealt to K interleaved rANS streams (row ts + r of a group goes
+to stream r mod K, K rows popped per round). Each stream's encoder walks its
+own symbols backwards (RevOrder in nx_order.hpp, compiled here for the
+host). The test restates the decoder's loop and checks, for every stream,
+that the encoder's walk is exactly its reverse, and that the streams
+together cover every symbol of the lane once, for lanes narrower than h + 1
+columns, single rows and columns, and ragged group sizes.
+"""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2201_05213_amd", "csrc")
+
+DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include <tuple>
+#include <algorithm>
+#include "nx_order.hpp"
+using namespace nx;
+typedef std::tuple<int, int, int> Sym;  // row, column, channel
+
+// the decoder's pop order, stream by stream
+static std::vector<std::vector<Sym>> decoder_order(int Hl, int Wl, int h, int K) {
+  const int o = h + 1;
+  std::vector<std::vector<Sym>> dec(K);
+  for (int t = 0; t < Wl + o * (Hl - 1); ++t) {
+    int ilo, ihi;
+    step_rows(t, Hl, Wl, o, ilo, ihi);
+    for (int ts = ilo; ts <= ihi; ts += 16) {
+      const int na = std::min(16, ihi - ts + 1);
+      for (int c = 0; c < 3; ++c)
+        for (int q0 = 0; q0 < na; q0 += K)
+          for (int k = 0; k < K; ++k)
+            if (q0 + k < na) dec[k].push_back(Sym(ts + q0 + k, t - o * (ts + q0 + k), c));
+    }
+  }
+  return dec;
+}
+
+int main() {
+  int cases = 0, bad = 0;
+  for (int h = 1; h <= 3; ++h)
+    for (int K : {1, 2, 4})
+      for (int Hl = 1; Hl <= 70; Hl += (Hl < 6 ? 1 : 11))
+        for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13)) {
+          ++cases;
+          const auto dec = decoder_order(Hl, Wl, h, K);
+          std::vector<Sym> all;
+          for (int k = 0; k < K; ++k) {
+            RevOrder it;
+            it.init(Hl, Wl, h + 1, 0, K, k);
+            std::vector<Sym> enc;
+            while (!it.done && enc.size() <= (size_t)Hl * Wl * 3) {
+              enc.push_back(Sym(it.i, it.col(), it.c));
+              it.advance();
+            }
+            std::reverse(enc.begin(), enc.end());
+            if (enc != dec[k]) {
+              if (bad < 5) printf("order mismatch h=%d K=%d %dx%d stream %d\n", h, K, Hl, Wl, k);
+              ++bad;
+            }
+            all.insert(all.end(), enc.begin(), enc.end());
+          }
+          std::sort(all.begin(), all.end());
+          bool cover = all.size() == (size_t)Hl * Wl * 3;
+          for (size_t n = 0; cover && n < all.size(); ++n) {
+            const int i = (int)(n / (3 * Wl)), j = (int)(n / 3 % Wl), c = (int)(n % 3);
+            cover = all[n] == Sym(i, j, c);
+          }
+          if (!cover) {
+            if (bad < 5) printf("coverage h=%d K=%d %dx%d\n", h, K, Hl, Wl);
+            ++bad;
+          }
+        }
+  // raster: one stream, rows, columns, channels, backwards
+  for (int Hl = 1; Hl <= 9; ++Hl)
+    for (int Wl = 1; Wl <= 9; ++Wl) {
+      ++cases;
+      RevOrder it;
+      it.init(Hl, Wl, 4, 1, 1, 0);
+      int n = Hl * Wl * 3;
+      while (!it.done) {
+        --n;
+        if (Sym(it.i, it.col(), it.c) != Sym(n / (3 * Wl), n / 3 % Wl, n % 3)) ++bad;
+        it.advance();
+      }
+      if (n != 0) ++bad;
+    }
+  printf("%d cases %d bad\n", cases, bad);
+  return bad != 0;
+}
+"""
+
+
+def test_encoder_walk_reverses_decoder_order(tmp_path):
+    src = tmp_path / "order.cpp"
+    exe = tmp_path / "order"
+    src.write_text(DRIVER)
+    cmd = ["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I", "/opt/rocm/include",
+           str(src), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail("host build of nx_order.hpp failed:\n" + r.stderr[-2000:])
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout
+    assert " 0 bad" in r.stdout
