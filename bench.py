@@ -160,6 +160,39 @@ def main():
         log(f"[bench] profile mode: {CALIB_BYTES} B copy x3 done")
         return
 
+    # encoder: the whole nellox_encode (full-image pass, per-stream rANS,
+    # container assembly), and the full-image pass alone (the fused per-pixel
+    # routine: gather, network, mixture, two CDF points per channel), timed
+    # through the symbol hook that runs just that pass
+    enc_ws = m.workspace(arr, len(ts), o)
+    for _ in range(2):
+        m.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave, ws=enc_ws, sync=False)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    nrep = max(3, args.steps // 2)
+    ev[0].record(stream)
+    for _ in range(nrep):
+        m.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave, ws=enc_ws, sync=False)
+    ev[1].record(stream)
+    sym_buf = torch.empty(npx * 3, dtype=torch.int32, device=dev)
+    in_arr = nx._images(ts)
+    o1 = nx._opts(nx.WAVEFRONT, patch)
+    for _ in range(nrep):
+        rc = L.nellox_debug_symbols(m._h, len(ts), in_arr, ctypes.byref(o1), sym_buf.data_ptr(), None,
+                                    enc_ws.data_ptr(), enc_ws.numel(), ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"nellox_debug_symbols returned {rc}")
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    enc_step = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
+    pass_step = ev[1].elapsed_time(ev[2]) / 1e3 / nrep
+    enc_rec = {"px_per_s": npx / enc_step, "ms": enc_step * 1e3, "pass_ms": pass_step * 1e3,
+               "pass_tflops": flops_per_px * npx / pass_step / 1e12,
+               "pass_frac_fp32_peak": flops_per_px * npx / pass_step / PEAK_FP32}
+    log(f"[bench] encode {enc_step * 1e3:.2f} ms ({npx / enc_step / 1e6:.0f} Mpx/s); full-image pass "
+        f"{pass_step * 1e3:.2f} ms, {enc_rec['pass_tflops']:.1f} TFLOP/s ({enc_rec['pass_frac_fp32_peak'] * 100:.1f}% "
+        f"of FP32 peak)")
+
     # one 1024x1024 image alone: wavefront+patch latency
     one = [ts[0]]
     d1, o1 = m.encode(one, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave)
@@ -308,6 +341,7 @@ def main():
         "speedup_vs_raster_1024": raster_full_s / one_s,
         "batch_px_per_s_vs_raster": value / raster_pxs,
         "encode_s_untimed": enc_s,
+        "encode": enc_rec,
         "bits_per_dim": bpd,
         "gap_vs_oracle_ideal": gap,
         "roofline": {"bound": "mfma", "kernel": f"k_decode<{dims['h']},{dims['C']}>",

@@ -133,6 +133,29 @@ nellox_status nellox_decode_trace(const nellox_model* m, int32_t n, const uint8_
                                   const nellox_opts* opts, const nellox_image* out, int32_t* status,
                                   uint32_t* sym_dump, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- capturable decoding (batching) ----
+ * nellox_decode split in two: prepare validates the batch and writes its
+ * plan (per-image descriptors) into the workspace, with a host-to-device copy;
+ * run only launches kernels (no copies, no host waits), so a caller may
+ * capture it in a hipGraph and replay it. The plan ties the workspace to the
+ * output images: every run decodes into them, from whatever containers `in`
+ * and `in_offsets` hold when it executes. A plan is plain host data. */
+typedef struct {
+  int32_t n, order, interleave; /* images, decoding order, rANS streams per lane */
+  int32_t grid, waves;          /* launch shape: workgroups, waves per workgroup */
+  int64_t n_lanes;              /* patches (lanes) of the batch */
+  uint64_t model_hash;          /* the model the plan was made for */
+  int64_t ws_bytes;             /* workspace bytes the plan occupies */
+  int64_t desc_offset;          /* byte offset of the descriptors in the workspace */
+  int64_t counter_offset;       /* byte offset of the lane-queue counter */
+} nellox_decode_plan;
+
+nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nellox_image* out,
+                                    const nellox_opts* opts, void* ws, size_t ws_bytes, nellox_decode_plan* plan,
+                                    void* stream);
+nellox_status nellox_decode_run(const nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
+                                const uint64_t* in_offsets, int32_t* status, void* ws, void* stream);
+
 /* Continuous code length -log2 p(x) of each image under the model (Eq. 2's
  * objective): bits_per_px (nullable, device, sum of H*W floats) and
  * bits_total (device, n doubles). opts.patch_* selects the patch grid. */

@@ -15,7 +15,7 @@ from typing import Sequence
 
 import torch
 
-from ._lib import NelloxError, NelloxImage, NelloxOpts, check, load
+from ._lib import NelloxDecodePlan, NelloxError, NelloxImage, NelloxOpts, check, load
 
 __all__ = ["Model", "NelloxError", "load", "RASTER", "WAVEFRONT"]
 
@@ -137,6 +137,29 @@ class Model:
                 raise NelloxError(bad[0][1], f"nellox_decode (image {bad[0][0]})")
         return (imgs, status, dump[:sum(int(h) * int(w) for h, w in shapes) * 3]) if trace else (imgs, status)
 
+    def decode_prepare(self, out: Sequence[torch.Tensor], order: int = WAVEFRONT, patch=None, interleave: int = 1,
+                       ws: torch.Tensor | None = None):
+        """Plan a batch decode into the images `out` (preallocated, H x W x 3
+        uint8): returns (plan, ws). decode_run(plan, ...) then only launches
+        kernels and may be captured in a CUDA/HIP graph; keep `out` and `ws`
+        alive as long as the plan is used."""
+        L = load()
+        n = len(out)
+        o = _opts(order, patch, interleave)
+        arr = _images(out)
+        if ws is None:
+            ws = self.workspace(arr, n, o)
+        plan = NelloxDecodePlan()
+        check(L.nellox_decode_prepare(self._h, n, arr, ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(plan),
+                                      _stream(self.device)), "nellox_decode_prepare")
+        return plan, ws
+
+    def decode_run(self, plan, data: torch.Tensor, offsets: torch.Tensor, status: torch.Tensor, ws: torch.Tensor):
+        """Launch a prepared decode on the current stream (asynchronous;
+        status: int32 CUDA tensor of n entries, 0 = OK)."""
+        check(load().nellox_decode_run(self._h, ctypes.byref(plan), data.data_ptr(), offsets.data_ptr(),
+                                       status.data_ptr(), ws.data_ptr(), _stream(self.device)), "nellox_decode_run")
+
     def nll(self, imgs: Sequence[torch.Tensor], patch=None, per_pixel: bool = False):
         """Continuous code length -log2 p(x) per image (float64 CUDA tensor)."""
         L = load()
@@ -177,6 +200,19 @@ class Model:
         check(L.nellox_debug_cdf(self._h, arr, ctypes.byref(o), cdf.data_ptr(), ws.data_ptr(), ws.numel(),
                                  _stream(self.device)), "nellox_debug_cdf")
         return cdf
+
+
+def payload_bits(data, offsets) -> list:
+    """Coded bits per image: the stream payloads (final states and
+    renormalisation bytes), without the header and the stream table."""
+    d = bytes(data.cpu().numpy().tobytes()) if isinstance(data, torch.Tensor) else bytes(data)
+    o = offsets.cpu().tolist() if isinstance(offsets, torch.Tensor) else list(offsets)
+    out = []
+    for k in range(len(o) - 1):
+        c = d[o[k]:o[k + 1]]
+        nl = int.from_bytes(c[28:32], "little")
+        out.append(8 * (len(c) - 32 - 4 * nl * c[7]))
+    return out
 
 
 def peek(container: bytes):

@@ -21,6 +21,13 @@ class NelloxImage(ctypes.Structure):
     _fields_ = [("px", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
 
 
+class NelloxDecodePlan(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("order", ctypes.c_int32), ("interleave", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_lanes", ctypes.c_int64),
+                ("model_hash", ctypes.c_uint64), ("ws_bytes", ctypes.c_int64), ("desc_offset", ctypes.c_int64),
+                ("counter_offset", ctypes.c_int64)]
+
+
 # exported symbol -> (restype, argtypes)
 _P, _I32, _SZ, _U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_uint64
 _ST = ctypes.c_int
@@ -34,6 +41,8 @@ SIGNATURES = {
     "nellox_peek": (_ST, [_P, _SZ, _P, _P, _P]),
     "nellox_decode": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_decode_trace": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "nellox_decode_prepare": (_ST, [_P, _I32, _P, _P, _P, _SZ, _P, _P]),
+    "nellox_decode_run": (_ST, [_P, _P, _P, _P, _P, _P, _P]),
     "nellox_nll": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_symbols": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_cdf": (_ST, [_P, _P, _P, _P, _P, _SZ, _P]),

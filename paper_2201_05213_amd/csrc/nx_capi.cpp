@@ -140,7 +140,7 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
 }
 
 struct WsLayout {
-  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, total;
+  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, total;
 };
 
 WsLayout ws_layout(const Plan& P, int n) {
@@ -152,6 +152,7 @@ WsLayout ws_layout(const Plan& P, int n) {
   W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
   W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
   W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
+  W.partials = o; o = align256(o + 8LL * REDUCE_PARTS * std::max(n, 1));
   W.sym = o; o = align256(o + 12 * std::max<int64_t>(P.n_px, 1));
   W.slots = o; o = align256(o + std::max<int64_t>(P.slot_bytes, 1));
   W.total = o;
@@ -460,54 +461,98 @@ nellox_status nellox_peek(const uint8_t* c, size_t len, int32_t* H, int32_t* W, 
   return NELLOX_OK;
 }
 
-static nellox_status decode_impl(const nellox_model* mc, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
-                                 const nellox_opts* o, const nellox_image* outs, int32_t* status, uint32_t* dump,
-                                 void* ws, size_t ws_bytes, void* stream) {
-  nellox_model* m = const_cast<nellox_model*>(mc);
+static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image* outs, const nellox_opts* o,
+                                  void* ws, size_t ws_bytes, nellox_decode_plan* plan, void* stream) {
   if (check_model(m)) return NELLOX_E_ARG;
+  if (!plan) return fail(NELLOX_E_ARG, "plan is null");
   Plan P;
   nellox_status st = make_plan(n, outs, o, P, true);
   if (st) return st;
-  if (n > 0 && (!in || !in_offsets || !status || !ws)) return fail(NELLOX_E_ARG, "null pointer argument");
+  if (n > 0 && !ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
   if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  if (n > 0 && (st = upload_plan(m, P, (uint8_t*)ws, W, s))) return st;
+  // spread the lanes over every CU: waves per workgroup = lanes per CU
+  // (at most DECODE_WAVES), one workgroup per CU while lanes remain; the
+  // waves of a CU share its LDS (weights, pivot tables, cross-lane traffic)
+  const int cus = persistent_grid(m);
+  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
+  memset(plan, 0, sizeof(*plan));
+  plan->n = n;
+  plan->order = o->order;
+  plan->interleave = P.K;
+  plan->waves = waves;
+  plan->grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
+  plan->n_lanes = P.n_lanes;
+  plan->model_hash = m->hash;
+  plan->ws_bytes = W.total;
+  plan->desc_offset = W.desc;
+  plan->counter_offset = W.flags + 4;
+  hipError_t e = prepare_decode(m->h, m->Cp, P.K);
+  if (e != hipSuccess) return hip_fail(e, "decoder set-up");
+  return NELLOX_OK;
+}
+
+static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
+                              const uint64_t* in_offsets, int32_t* status, uint32_t* dump, void* ws, void* stream) {
+  if (check_model(m)) return NELLOX_E_ARG;
+  if (!plan || plan->model_hash != m->hash || plan->n < 0 || plan->waves < 1 || plan->waves > DECODE_WAVES ||
+      !valid_interleave(plan->interleave))
+    return fail(NELLOX_E_ARG, "plan does not belong to this model");
+  const int n = plan->n;
   if (n == 0) return NELLOX_OK;
+  if (!in || !in_offsets || !status || !ws) return fail(NELLOX_E_ARG, "null pointer argument");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
-  if ((st = upload_plan(m, P, w8, W, s))) return st;
-  int32_t* counter = (int32_t*)(w8 + W.flags) + 1;
+  int32_t* counter = (int32_t*)(w8 + plan->counter_offset);
   hipError_t e = launch_decode_prep(status, n, counter, s);
   if (e != hipSuccess) return hip_fail(e, "decode prep launch");
   DecArgs a{};
   a.w = m->dw;
   a.wfloats = m->wfloats;
   a.nb = m->nb;
-  a.desc = (const ImgDesc*)(w8 + W.desc);
+  a.desc = (const ImgDesc*)(w8 + plan->desc_offset);
   a.n_img = n;
-  a.n_lanes = P.n_lanes;
-  a.order = o->order;
-  a.K = P.K;
+  a.n_lanes = plan->n_lanes;
+  a.order = plan->order;
+  a.K = plan->interleave;
   a.model_hash = m->hash;
   a.in = in;
   a.in_off = in_offsets;
   a.status = status;
   a.counter = counter;
   a.sym_dump = dump;
-  // spread the lanes over every CU: waves per workgroup = lanes per CU
-  // (at most DECODE_WAVES), one workgroup per CU while lanes remain; the
-  // waves of a CU share its LDS (weights, pivot tables, cross-lane traffic)
-  const int cus = persistent_grid(m);
-  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
-  const int grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
-  e = launch_decode(m->h, m->Cp, a, grid, waves, s);
+  e = launch_decode(m->h, m->Cp, a, plan->grid, plan->waves, s);
   if (e != hipSuccess) return hip_fail(e, "decoder launch");
   return NELLOX_OK;
+}
+
+static nellox_status decode_impl(const nellox_model* mc, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
+                                 const nellox_opts* o, const nellox_image* outs, int32_t* status, uint32_t* dump,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  nellox_model* m = const_cast<nellox_model*>(mc);
+  if (n > 0 && (!in || !in_offsets || !status || !ws)) return fail(NELLOX_E_ARG, "null pointer argument");
+  nellox_decode_plan plan;
+  nellox_status st = prepare_impl(m, n, outs, o, ws, ws_bytes, &plan, stream);
+  if (st) return st;
+  return run_impl(m, &plan, in, in_offsets, status, dump, ws, stream);
 }
 
 nellox_status nellox_decode(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
                             const nellox_opts* o, const nellox_image* out, int32_t* status, void* ws, size_t ws_bytes,
                             void* stream) {
   return decode_impl(m, n, in, in_offsets, o, out, status, nullptr, ws, ws_bytes, stream);
+}
+
+nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nellox_image* out, const nellox_opts* opts,
+                                    void* ws, size_t ws_bytes, nellox_decode_plan* plan, void* stream) {
+  return prepare_impl(const_cast<nellox_model*>(m), n, out, opts, ws, ws_bytes, plan, stream);
+}
+
+nellox_status nellox_decode_run(const nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
+                                const uint64_t* in_offsets, int32_t* status, void* ws, void* stream) {
+  return run_impl(const_cast<nellox_model*>(m), plan, in, in_offsets, status, nullptr, ws, stream);
 }
 
 nellox_status nellox_decode_trace(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
@@ -533,7 +578,7 @@ nellox_status nellox_nll(const nellox_model* mc, int32_t n, const nellox_image* 
   if ((st = upload_plan(m, P, w8, W, s))) return st;
   float* bits = bits_per_px ? bits_per_px : (float*)(w8 + W.bits);
   if ((st = run_pass(m, P, w8, W, 1, nullptr, bits, nullptr, s))) return st;
-  hipError_t e = launch_reduce_bits((const ImgDesc*)(w8 + W.desc), n, bits, bits_total, s);
+  hipError_t e = launch_reduce_bits((const ImgDesc*)(w8 + W.desc), n, bits, (double*)(w8 + W.partials), bits_total, s);
   if (e != hipSuccess) return hip_fail(e, "reduction launch");
   return NELLOX_OK;
 }
@@ -553,10 +598,10 @@ nellox_status nellox_debug_symbols(const nellox_model* mc, int32_t n, const nell
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
   if ((st = upload_plan(m, P, w8, W, s))) return st;
-  float* bits = (float*)(w8 + W.bits);
+  float* bits = ideal ? (float*)(w8 + W.bits) : nullptr;  // the pass alone when no sum is asked for
   if ((st = run_pass(m, P, w8, W, 0, sym, bits, nullptr, s))) return st;
   if (ideal) {
-    hipError_t e = launch_reduce_bits((const ImgDesc*)(w8 + W.desc), n, bits, ideal, s);
+    hipError_t e = launch_reduce_bits((const ImgDesc*)(w8 + W.desc), n, bits, (double*)(w8 + W.partials), ideal, s);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
   }
   return NELLOX_OK;

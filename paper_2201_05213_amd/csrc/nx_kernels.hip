@@ -566,21 +566,32 @@ __global__ void k_decode_prep(int32_t* status, int n_img, int32_t* counter) {
   if (i == 0) *counter = 0;
 }
 
-// per image: sum of per-pixel bits in double, fixed order (thread-strided
-// partial sums, then a fixed tree)
-__global__ void __launch_bounds__(256) k_reduce_bits(const ImgDesc* desc, const float* bits, double* out) {
+// per image: sum of per-pixel bits in double, in a fixed order: block (n, r)
+// sums part r of image n (thread-strided partial sums, then a fixed tree),
+// then one thread per image adds the REDUCE_PARTS partials in order
+__global__ void __launch_bounds__(256) k_reduce_bits(const ImgDesc* desc, const float* bits, double* part_out) {
   __shared__ double part[256];
   const ImgDesc D = desc[blockIdx.x];
   const int64_t npx = (int64_t)D.H * D.W;
+  const int64_t per = (npx + REDUCE_PARTS - 1) / REDUCE_PARTS;
+  const int64_t lo = (int64_t)blockIdx.y * per, hi = lo + per < npx ? lo + per : npx;
   double s = 0.0;
-  for (int64_t k = threadIdx.x; k < npx; k += 256) s += (double)bits[D.px_base + k];
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s += (double)bits[D.px_base + k];
   part[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+  if (threadIdx.x == 0) part_out[(int64_t)blockIdx.x * REDUCE_PARTS + blockIdx.y] = part[0];
+}
+
+__global__ void k_reduce_final(const double* part, int n_img, double* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_img) return;
+  double s = 0.0;
+  for (int r = 0; r < REDUCE_PARTS; ++r) s += part[(int64_t)n * REDUCE_PARTS + r];
+  out[n] = s;
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -607,10 +618,28 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
 template <int H_, int C_, bool TRACE, int K>
 static hipError_t decode_tt(const DecArgs& a, int grid, int waves, hipStream_t s) {
   const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * PIV_WORDS * 4;
-  hipError_t e = allow_lds(k_decode<H_, C_, TRACE, K>, lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K>), dim3(grid), dim3(waves * 64), lds, s, a);
   return hipGetLastError();
+}
+
+// the decoder's dynamic LDS limit, raised to the device maximum once per
+// kernel before any launch (not a stream operation: kept out of the launch
+// path, which a caller may capture)
+template <int H_, int C_, int K>
+static hipError_t decode_setup_k() {
+  int dev = 0, lim = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, K>, (size_t)lim);
+  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, true, K>, (size_t)lim);
+  return e;
+}
+
+template <int H_, int C_>
+static hipError_t decode_setup(int K) {
+  if (K == 2) return decode_setup_k<H_, C_, 2>();
+  if (K == 4) return decode_setup_k<H_, C_, 4>();
+  return decode_setup_k<H_, C_, 1>();
 }
 
 template <int H_, int C_, int K>
@@ -643,6 +672,8 @@ hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s)
   NX_DISPATCH(pass_t, h, C, a, grid, s);
 }
 
+hipError_t prepare_decode(int h, int C, int K) { NX_DISPATCH(decode_setup, h, C, K); }
+
 hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
   if (waves < 1 || waves > NWAVES_DEC) return hipErrorInvalidValue;
@@ -669,9 +700,11 @@ hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s) {
+hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* partials, double* out,
+                              hipStream_t s) {
   if (n_img == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_bits, dim3(n_img), dim3(256), 0, s, desc, bits, out);
+  hipLaunchKernelGGL(k_reduce_bits, dim3(n_img, REDUCE_PARTS), dim3(256), 0, s, desc, bits, partials);
+  hipLaunchKernelGGL(k_reduce_final, dim3((n_img + 63) / 64), dim3(64), 0, s, partials, n_img, out);
   return hipGetLastError();
 }
 

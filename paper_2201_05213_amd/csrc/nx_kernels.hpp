@@ -124,9 +124,16 @@ hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s)
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s);
-// waves per workgroup in 1..DECODE_WAVES (the LDS takes one pivot table per wave)
+// raise the decoder kernels' LDS limit (once, outside any stream capture)
+hipError_t prepare_decode(int h, int C, int K);
+// waves per workgroup in 1..DECODE_WAVES (the LDS takes one pivot table per wave);
+// prepare_decode must have run for (h, C, a.K)
 hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s);
-hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* out, hipStream_t s);
+// per-image FP64 sums of per-pixel bits, in a fixed order (partials: n_img
+// x REDUCE_PARTS doubles of scratch)
+constexpr int REDUCE_PARTS = 64;
+hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* partials, double* out,
+                              hipStream_t s);
 
 constexpr int TRAIN_BLOCK = 16 * 64;  // threads per workgroup of the per-tile training kernels
 hipError_t launch_swizzle(const float* params, int h, int C, int Cp, int nb, float* wimg, int64_t nw, float* wimgT,

@@ -238,3 +238,90 @@ def test_interleave_argument_checks(models, nx):
     data, offs = m.encode([t], order=1, interleave=2)
     with pytest.raises(nx.NelloxError):       # streams per lane must match the container
         m.decode(data, offs, [(8, 8)], order=1, interleave=4)
+
+
+# ---------------------------------------------------------------- batching
+def test_decode_graph_capture_and_replay(models, nx):
+    """A prepared decode captured in a graph: every replay (with eager work
+    in between) decodes exactly, also after new containers of the same
+    shapes are copied into the captured input buffers."""
+    say("[gpu] graph capture of a prepared decode, 8 uneven images, patch 32")
+    m, _, _ = models["B"]
+    imgs = synth.workload_images("uneven64", count=8)
+    ts = [cuda(i) for i in imgs]
+    ts2 = [cuda(np.ascontiguousarray(i[::-1, ::-1])) for i in imgs]
+    d1, o1 = m.encode(ts, order=1, patch=(32, 32))
+    d2, o2 = m.encode(ts2, order=1, patch=(32, 32))
+    buf = torch.zeros(max(d1.numel(), d2.numel()), dtype=torch.uint8, device="cuda")
+    offs = torch.zeros_like(o1)
+    buf[:d1.numel()].copy_(d1)
+    offs.copy_(o1)
+    outs = [torch.zeros_like(t) for t in ts]
+    plan, ws = m.decode_prepare(outs, order=1, patch=(32, 32))
+    status = torch.full((len(ts),), 7, dtype=torch.int32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        m.decode_run(plan, buf, offs, status, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        m.decode_run(plan, buf, offs, status, ws)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        status.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.abs().sum()) == 0, rep
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts)), rep
+    buf[:d2.numel()].copy_(d2)
+    offs.copy_(o2)
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.abs().sum()) == 0
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts2))
+
+
+@pytest.mark.parametrize("patch", [(32, 32), (64, 64)])
+def test_uneven64_one_launch(models, nx, patch):
+    """64 images of uneven sizes coded and decoded in one call each, with
+    patches: exact round trip, and bits within 0.1% of the oracle's ideal for
+    the same patch grid on sampled images."""
+    say(f"[gpu] uneven64, model B, patch {patch}")
+    m, om, _ = models["B"]
+    imgs = synth.workload_images("uneven64")
+    ts = [cuda(i) for i in imgs]
+    data, offs = m.encode(ts, order=1, patch=patch)
+    out, st = m.decode(data, offs, [i.shape[:2] for i in imgs], order=1, patch=patch)
+    for a, b in zip(out, ts):
+        assert torch.equal(a, b)
+    pb = nx.payload_bits(data, offs)
+    small = [k for k, i in enumerate(imgs) if i.shape[0] * i.shape[1] <= 96 * 128][:3]
+    ideal = sum(om.stats(imgs[k], ph=patch[0], pw=patch[1])["qbits"] for k in small)
+    got = float(sum(pb[k] for k in small))
+    say(f"[gpu] uneven64 patch {patch}: sampled gap {(got - ideal) / ideal * 100:.4f}% on {len(small)} images")
+    assert got <= ideal * 1.001
+
+
+def test_autotune_patch_and_streams(models, nx):
+    say("[gpu] autotune over patch x streams, 8 uneven images")
+    from paper_2201_05213_amd import tune
+
+    m, _, _ = models["B"]
+    ts = [cuda(i) for i in synth.workload_images("uneven64", count=8)]
+    choice, table = tune.autotune(m, ts, patches=((32, 32), (64, 64)), interleaves=(1, 2), reps=2)
+    say("[gpu] " + "; ".join(f"{r['patch']} K={r['interleave']}: {r['decode_ms']:.2f} ms {r['bits']} b" for r in table))
+    assert len(table) == 4 and choice in table
+    best = min(r["bits"] for r in table)
+    assert choice["bits"] <= best * 1.001
+    data, offs = m.encode(ts, order=1, patch=choice["patch"], interleave=choice["interleave"])
+    out, _ = m.decode(data, offs, [t.shape[:2] for t in ts], order=1, patch=choice["patch"],
+                      interleave=choice["interleave"])
+    assert all(torch.equal(a, b) for a, b in zip(out, ts))
