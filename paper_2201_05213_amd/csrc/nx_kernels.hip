@@ -19,7 +19,10 @@ namespace nx {
 constexpr int NWAVES = 16;      // waves per full-image-pass workgroup (all share the LDS weights)
 constexpr int NWAVES_DEC = DECODE_WAVES;  // waves per decoder workgroup
 constexpr int PIV_WORDS = 256;            // per decoder wave: 16 pixels x 16 pivot CDF values
-static_assert(DECODE_LDS_EXTRA == NWAVES_DEC * PIV_WORDS * 4, "decoder LDS budget");
+constexpr int PRM_STRIDE = 36;            // floats per pixel: (w, a, b) of 12 component slots
+constexpr int PRM_WORDS = 16 * PRM_STRIDE;  // per decoder wave: one channel's mixtures of 16 pixels
+constexpr int WAVE_LDS_WORDS = PIV_WORDS + PRM_WORDS;
+static_assert(DECODE_LDS_EXTRA == NWAVES_DEC * WAVE_LDS_WORDS * 4, "decoder LDS budget");
 
 NXD int find_img(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane) {
   int lo = 0, hi = n - 1;
@@ -334,6 +337,98 @@ struct ByteStage {
   }
 };
 
+// ------------------------------------------------------------------ four-row decoding
+// With four streams per lane, the wave's 16-lane rows work independently:
+// row g searches the symbol of stream g while every lane evaluates all ten
+// mixture components at its own point, so no cross-row reduction is needed.
+// A pixel's mixture for the channel is staged in LDS as (w, a, b) of
+// component m at floats 3m..3m+2 of the pixel's row of the table.
+struct Mix10 {
+  float w[10], a[10], b[10];
+};
+
+NXD void load_mix10(Mix10& P, const float* prm, int pix) {
+  const float4* s = (const float4*)(prm + pix * PRM_STRIDE);
+  float v[32];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float4 t = s[i];
+    v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
+  }
+#pragma unroll
+  for (int m = 0; m < 10; ++m) {
+    P.w[m] = v[3 * m];
+    P.a[m] = v[3 * m + 1];
+    P.b[m] = v[3 * m + 2];
+  }
+}
+
+// F at bin edge k over all ten components in this lane. The terms and the
+// additions are those of cdf_eval: per lane group g the sum
+// s_g = (t_g + t_{g+4}) + t_{g+8} (groups 2 and 3 add an exact zero), then
+// (s_0 + s_1) + (s_2 + s_3); so the value is bit-identical to the encoder's.
+NXD float cdf_eval10(int k, const Mix10& P) {
+  const float e = bin_edge(k);
+  float t[10];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) {
+    const float x = __builtin_amdgcn_exp2f(__builtin_fmaf(-e, P.a[m], P.b[m]));
+    t[m] = P.w[m] * __builtin_amdgcn_rcpf(1.0f + x);
+  }
+  const float s0 = (t[0] + t[4]) + t[8];
+  const float s1 = (t[1] + t[5]) + t[9];
+  const float s2 = t[2] + t[6];
+  const float s3 = t[3] + t[7];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// bits of row g in a wave-wide ballot, counted
+NXD int row_count(uint64_t bal, int g) {
+  const uint32_t half = (g & 2) ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+  return __builtin_popcount((half >> ((g & 1) << 4)) & 0xffffu);
+}
+
+// One stream per row: state, position and a 64-byte window of its bytes,
+// 4 bytes per lane of the row (every value uniform within the row).
+struct RowStream {
+  const uint8_t* S;
+  uint32_t len, base, pos, x, word;
+  // lanes of the row load the window [at, at + 64) (clamped, unconditional loads)
+  NXD void fill(uint32_t at, int p) {
+    base = at;
+    const gbytes gs = as_global(S);
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t o = at + 4 * (uint32_t)p + b;
+      const uint32_t byte = gs[o < len ? o : len - 1];
+      v |= (o < len ? byte : 0u) << (8 * b);
+    }
+    word = v;
+  }
+  // byte at q of this row's window (every lane of the wave takes part)
+  NXD uint32_t byte_at(uint32_t q, int g) const {
+    const uint32_t off = q - base;
+    const uint32_t v = (uint32_t)__shfl((int)word, (g << 4) | (int)((off >> 2) & 15u));
+    return (v >> (8 * (off & 3u))) & 255u;
+  }
+  // renormalisation after a pop of this row (as ByteStage::renorm): the window
+  // is moved first where it would not hold pos + 1
+  NXD void renorm(bool act, int p, int g) {
+    const bool need = pos + 2u > base + 64u && pos < len;
+    if (__ballot(need) != 0ull) {
+      if (need) fill(pos & ~3u, p);
+    }
+    const uint32_t b0 = byte_at(pos, g), b1 = byte_at(pos + 1u, g);
+    const bool r0 = act && x < RANS_L && pos < len;
+    x = r0 ? ((x << 8) | b0) : x;
+    pos += r0 ? 1u : 0u;
+    const bool r1 = act && x < RANS_L && pos < len;
+    x = r1 ? ((x << 8) | b1) : x;
+    pos += r1 ? 1u : 0u;
+  }
+};
+
 // K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
 // streams k) per iteration, their searches independent of each other.
 template <int H_, int C_, bool TRACE, int K>
@@ -370,30 +465,55 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     A.status[n] = ST_MISMATCH;
     return;
   }
-  ByteStage R[K];
-  uint32_t x[K], pos[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int64_t e = (int64_t)q * K + k;  // stream table entry
+  // K <= 2: the streams' states are scalar (one search after another);
+  // K = 4: one stream per 16-lane row, its state held by the row
+  constexpr int KS = K == 4 ? 1 : K;
+  ByteStage R[KS];
+  uint32_t x[KS], pos[KS];
+  RowStream RS;
+  if constexpr (K == 4) {
+    const int64_t e = (int64_t)q * K + g;  // stream table entry of this row
     uint32_t lend = 0, lstart = 0;
+    bool okr = ok;
     if (ok) {
-      lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * e));
-      lstart = e > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (e - 1))) : 0u;
-      ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+      lend = rd_u32(C + HDR_BYTES + 4 * e);
+      lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
+      okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
     }
-    R[k].S = C + pay + lstart;
-    R[k].len = lend - lstart;
+    ok = __ballot(okr) == ~0ull;
+    RS.S = C + pay + lstart;
+    RS.len = lend - lstart;
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t e = (int64_t)q * K + k;  // stream table entry
+      uint32_t lend = 0, lstart = 0;
+      if (ok) {
+        lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * e));
+        lstart = e > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (e - 1))) : 0u;
+        ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+      }
+      R[k].S = C + pay + lstart;
+      R[k].len = lend - lstart;
+    }
   }
   if (!ok) {
     A.status[n] = ST_CORRUPT;
     return;
   }
+  if constexpr (K == 4) {
+    RS.fill(0, p);
+    RS.x = (uint32_t)__shfl((int)RS.word, g << 4);  // bytes 0..3, little endian
+    RS.pos = 4;
+  } else {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    R[k].fill(0, lane);
-    x[k] = R[k].byte_at(0) | (R[k].byte_at(1) << 8) | (R[k].byte_at(2) << 16) | (R[k].byte_at(3) << 24);
-    pos[k] = 4;
+    for (int k = 0; k < K; ++k) {
+      R[k].fill(0, lane);
+      x[k] = R[k].byte_at(0) | (R[k].byte_at(1) << 8) | (R[k].byte_at(2) << 16) | (R[k].byte_at(3) << 24);
+      pos[k] = 4;
+    }
   }
+  float* prm = (float*)(piv + PIV_WORDS);
   uint8_t* img = D.px;
   const int o = H_ + 1;
   const bool raster = A.order == 0;
@@ -427,6 +547,77 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       for (int c = 0; c < 3; ++c) {
         Chan Q;
         chan_params(M, c, xr, xg, Q);
+        if constexpr (K == 4) {
+          // stage the channel's mixtures: lane (p, g) holds components g + 4 j
+          float* mine = prm + p * PRM_STRIDE;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int m = g + 4 * j;
+            mine[3 * m] = Q.w[j];
+            mine[3 * m + 1] = Q.a[j];
+            mine[3 * m + 2] = Q.b[j];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // pivots of pixel p: lane group g evaluates j = 4 g .. 4 g + 3
+          // (cdf at k = 16 (j + 1); j = 15 stands for k = 256)
+          {
+            Mix10 P;
+            load_mix10(P, prm, p);
+            uint32_t pvv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int j = 4 * g + i;
+              const int kk = min(16 * (j + 1), 255);
+              const uint32_t v = cdf_quant(kk, cdf_eval10(kk, P));
+              pvv[i] = j < 15 ? v : CDF_TOTAL;
+            }
+            *(uint4*)(piv + p * 16 + 4 * g) = make_uint4(pvv[0], pvv[1], pvv[2], pvv[3]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // pops: row g takes row ts + q0 + g of the group (stream g)
+          for (int q0 = 0; q0 < na; q0 += 4) {
+            const int pr = q0 + g;
+            const bool act = pr < na;
+            const int prc = min(pr, 15);
+            Mix10 P;
+            load_mix10(P, prm, prc);
+            const uint32_t pv = piv[prc * 16 + p];
+            const uint32_t slot = RS.x & 0xffffu;
+            const int b = row_count(__ballot(pv <= slot), g);
+            const int k2 = 16 * b + p;
+            const uint32_t c2 = cdf_quant(k2, cdf_eval10(max(k2, 1), P));
+            const int cnt = row_count(__ballot(c2 <= slot) & 0xfffefffefffefffeull, g);
+            const int sy = 16 * b + cnt;
+            const int rb = g << 4;
+            const uint32_t lo_r = (uint32_t)__shfl((int)pv, rb | ((b + 15) & 15));
+            const uint32_t st_r = (uint32_t)__shfl((int)c2, rb | cnt);
+            const uint32_t nc_r = (uint32_t)__shfl((int)c2, rb | ((cnt + 1) & 15));
+            const uint32_t np_r = (uint32_t)__shfl((int)pv, rb | b);
+            const uint32_t lo = b == 0 ? 0u : lo_r;
+            const uint32_t start = cnt == 0 ? lo : st_r;
+            const uint32_t freq = (cnt < 15 ? nc_r : np_r) - start;
+            const uint32_t xn = freq * (RS.x >> 16) + slot - start;
+            RS.x = act ? xn : RS.x;
+            RS.renorm(act, p, g);
+            // the symbol of pixel p (decoded by row p - q0) to all its lanes
+            const int src = p - q0;
+            const int sv = __shfl(sy, (src & 3) << 4);
+            if (src >= 0 && src < 4) {
+              if (c == 0) xv[0] = sv;
+              else if (c == 1) xv[1] = sv;
+              else xv[2] = sv;
+            }
+            if (TRACE && act && p == 0) {
+              const int ii = ts + pr;
+              const int jj = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * ii;
+              dump[((int64_t)(y0 + ii) * D.W + (x0 + jj)) * 3 + c] = start | (freq << 16);
+            }
+          }
+        } else {
         // pivot CDF values of every pixel of the group: cdf at k = 16 (j + 1),
         // j = 0..14, and 2^16 for k = 256 (independent evaluations)
 #pragma unroll 5
@@ -518,6 +709,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             }
           }
         }
+        }  // K < 4
         if (c == 0) {
           posterior(M, xv[0], Q.mu, Q.is, has2);
           xr = normalise(xv[0]);
@@ -537,8 +729,12 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     }
   }
   bool clean = true;
+  if constexpr (K == 4) {
+    clean = __ballot(RS.x == RANS_X0 && RS.pos == RS.len) == ~0ull;
+  } else {
 #pragma unroll
-  for (int k = 0; k < K; ++k) clean = clean && x[k] == RANS_X0 && pos[k] == R[k].len;
+    for (int k = 0; k < K; ++k) clean = clean && x[k] == RANS_X0 && pos[k] == R[k].len;
+  }
   if (!clean) A.status[n] = ST_CORRUPT;
 }
 
@@ -548,7 +744,7 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   float* w = (float*)smem_f4;
   load_weights(w, A.w, A.wfloats);
   const int lane = threadIdx.x & 63;
-  uint32_t* piv = (uint32_t*)(w + A.wfloats) + (threadIdx.x >> 6) * PIV_WORDS;
+  uint32_t* piv = (uint32_t*)(w + A.wfloats) + (threadIdx.x >> 6) * WAVE_LDS_WORDS;
   for (;;) {
     // one queue pop per wave, by its first active lane, broadcast
     const int leader = uniform(lane);
@@ -617,7 +813,7 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
 
 template <int H_, int C_, bool TRACE, int K>
 static hipError_t decode_tt(const DecArgs& a, int grid, int waves, hipStream_t s) {
-  const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * PIV_WORDS * 4;
+  const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * WAVE_LDS_WORDS * 4;
   hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K>), dim3(grid), dim3(waves * 64), lds, s, a);
   return hipGetLastError();
 }

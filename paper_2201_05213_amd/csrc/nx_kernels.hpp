@@ -114,9 +114,9 @@ struct GradReduceArgs {
 };
 
 // decoder workgroup shape: waves per workgroup and the LDS it needs beyond
-// the weight image (a pivot table per wave)
+// the weight image (per wave a pivot table and a mixture table)
 constexpr int DECODE_WAVES = 12;
-constexpr int DECODE_LDS_EXTRA = DECODE_WAVES * 256 * 4;
+constexpr int DECODE_LDS_EXTRA = DECODE_WAVES * (256 + 16 * 36) * 4;
 
 // host launchers (return hipError_t of the launch); h in {1,2,3}, C in {16,32,64}
 bool supported(int h, int C);
