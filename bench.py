@@ -4,8 +4,9 @@ same GPU's raster decode, bits/dim gap vs the FP64 oracle.
 Workload (synthetic, seeded): 4 images of 1024x1024 and 2 of 2048x1536 uint8
 RGB (smooth random fields, sigma 4 px, 20 step edges, +-3 integer noise),
 coded with the h=3, 64-channel, 2-block local model (random-init weights) in
-the wavefront order with independent 64x64 patches. One timed step = one
-decode of the whole batch from containers already resident in HBM.
+the wavefront order with independent 64x64 patches, each patch one lane of
+4 interleaved rANS streams. One timed step = one decode of the whole batch
+from containers already resident in HBM.
 
 Prints one JSON line (see the keys below); --gpus N > 1 is refused: this
 path runs on one GPU.
@@ -28,9 +29,9 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # HBM bytes per decoder launch on this workload from two counter passes
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a
 # 256 MiB device copy; valid only for the kernel sources they were taken on
-DECODE_TRAFFIC = {"src_sha": "59374c4a388a1d4c", "fetch_kib": 38388.1, "write_kib": 35403.2,
+DECODE_TRAFFIC = {"src_sha": "ef4822965f12ce85", "fetch_kib": 39001.5, "write_kib": 33918.1,
                   "fetch_scale": 1.9998, "write_scale": 1.0}
-KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp")
+KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
 
 def kernel_sources_sha() -> str:
@@ -66,7 +67,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--patch", type=int, default=64)
-    ap.add_argument("--interleave", type=int, default=1, help="rANS streams per lane (1, 2 or 4)")
+    ap.add_argument("--interleave", type=int, default=4, help="rANS streams per lane (1, 2 or 4)")
     ap.add_argument("--raster-rows", type=int, default=32,
                     help="rows of the 1024-wide strip the raster baseline decodes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
