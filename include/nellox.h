@@ -175,6 +175,14 @@ nellox_status nellox_debug_symbols(const nellox_model* m, int32_t n, const nello
 nellox_status nellox_debug_cdf(const nellox_model* m, const nellox_image* img, const nellox_opts* opts,
                                int32_t* cdf, void* ws, size_t ws_bytes, void* stream);
 
+/* Exhaustive check of the property the quantised CDF's monotonicity rests on
+ * (every symbol frequency >= 1): over every finite FP32 value in increasing
+ * order, counts adjacent pairs where the device's exp2 decreases
+ * (counts[0]), where its reciprocal increases on [1, FLT_MAX] (counts[1]),
+ * where rcp(1 + exp2(z)) increases (counts[2]); counts[3] = pairs checked.
+ * counts: 4 device uint64. */
+nellox_status nellox_debug_check_monotone(uint64_t* counts, void* stream);
+
 /* ---- training (the objective of Eq. 2: the model's code length, and its
  * gradient; Sec. 2.1 model) ----
  * These calls take the parameters directly instead of a model handle, so an

@@ -202,6 +202,16 @@ class Model:
         return cdf
 
 
+def debug_check_monotone(device=None) -> dict:
+    """Scan every finite FP32 value on the GPU and count order violations of
+    the hardware exp2, reciprocal and rcp(1 + exp2(z)) (see nellox.h)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    check(load().nellox_debug_check_monotone(counts.data_ptr(), _stream(dev)), "nellox_debug_check_monotone")
+    c = counts.cpu().tolist()
+    return {"exp2_decreasing": c[0], "rcp_increasing": c[1], "sigmoid_increasing": c[2], "pairs": c[3]}
+
+
 def payload_bits(data, offsets) -> list:
     """Coded bits per image: the stream payloads (final states and
     renormalisation bytes), without the header and the stream table."""

@@ -607,6 +607,13 @@ nellox_status nellox_debug_symbols(const nellox_model* mc, int32_t n, const nell
   return NELLOX_OK;
 }
 
+nellox_status nellox_debug_check_monotone(uint64_t* counts, void* stream) {
+  if (!counts) return fail(NELLOX_E_ARG, "counts is null");
+  hipError_t e = launch_check_monotone((unsigned long long*)counts, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "monotonicity check launch");
+  return NELLOX_OK;
+}
+
 nellox_status nellox_debug_cdf(const nellox_model* mc, const nellox_image* img, const nellox_opts* o, int32_t* cdf,
                                void* ws, size_t ws_bytes, void* stream) {
   nellox_model* m = const_cast<nellox_model*>(mc);

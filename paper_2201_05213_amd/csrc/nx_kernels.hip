@@ -790,6 +790,59 @@ __global__ void k_reduce_final(const double* part, int n_img, double* out) {
   out[n] = s;
 }
 
+// ------------------------------------------------------------------ monotonicity check
+// The quantised CDF is monotone in k (every frequency >= 1) only if the
+// hardware exp2 is non-decreasing and the reciprocal non-increasing on the
+// arguments cdf_eval gives them. This scans every finite FP32 value in
+// increasing order, a chunk of consecutive values per thread, and counts
+// adjacent pairs that break the order: out[0] exp2 on all finite inputs,
+// out[1] rcp on [1, FLT_MAX], out[2] rcp(1 + exp2(z)) (non-increasing in z) on
+// all finite z, out[3] pairs checked.
+constexpr uint32_t MONO_NEG = 0x7F800000u;  // finite negative bit patterns (-FLT_MAX .. -0)
+constexpr uint64_t MONO_ALL = 2ull * MONO_NEG;
+constexpr uint32_t MONO_CHUNK = 4096;
+
+NXD float mono_value(uint64_t i) {  // i-th finite float in increasing order
+  const uint32_t b = i < MONO_NEG ? 0xFF7FFFFFu - (uint32_t)i : (uint32_t)(i - MONO_NEG);
+  return __uint_as_float(b);
+}
+
+__global__ void __launch_bounds__(256) k_check_monotone(unsigned long long* out) {
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t lo = t * MONO_CHUNK;
+  unsigned long long bad_exp = 0, bad_rcp = 0, bad_sig = 0, pairs = 0;
+  if (lo < MONO_ALL) {
+    const uint64_t hi = lo + MONO_CHUNK < MONO_ALL ? lo + MONO_CHUNK : MONO_ALL;
+    const uint64_t first = lo > 0 ? lo - 1 : 0;
+    float z = mono_value(first);
+    float pe = __builtin_amdgcn_exp2f(z);
+    float ps = __builtin_amdgcn_rcpf(1.0f + pe);
+    float pr = __builtin_amdgcn_rcpf(z);
+    for (uint64_t i = first + 1; i < hi; ++i) {
+      z = mono_value(i);
+      const float e = __builtin_amdgcn_exp2f(z);
+      const float sg = __builtin_amdgcn_rcpf(1.0f + e);
+      const float r = __builtin_amdgcn_rcpf(z);
+      bad_exp += e < pe ? 1 : 0;
+      bad_sig += sg > ps ? 1 : 0;
+      // rcp on [1, FLT_MAX]: both values of the pair at or above 1
+      bad_rcp += (mono_value(i - 1) >= 1.0f && r > pr) ? 1 : 0;
+      ++pairs;
+      pe = e;
+      ps = sg;
+      pr = r;
+    }
+  }
+  if (bad_exp) atomicAdd(out + 0, bad_exp);
+  if (bad_rcp) atomicAdd(out + 1, bad_rcp);
+  if (bad_sig) atomicAdd(out + 2, bad_sig);
+  if (pairs) atomicAdd(out + 3, pairs);
+}
+
+__global__ void k_zero4(unsigned long long* out) {
+  if (threadIdx.x < 4) out[threadIdx.x] = 0;
+}
+
 // ------------------------------------------------------------------ host launchers
 bool supported(int h, int C) {
   return (h == 3 && (C == 16 || C == 32 || C == 64)) || (h == 2 && (C == 16 || C == 32 || C == 64)) ||
@@ -904,4 +957,13 @@ hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits,
   return hipGetLastError();
 }
 
+}  // namespace nx
+
+namespace nx {
+hipError_t launch_check_monotone(unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero4, dim3(1), dim3(64), 0, s, out);
+  const uint64_t threads = (MONO_ALL + MONO_CHUNK - 1) / MONO_CHUNK;
+  hipLaunchKernelGGL(k_check_monotone, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, out);
+  return hipGetLastError();
+}
 }  // namespace nx

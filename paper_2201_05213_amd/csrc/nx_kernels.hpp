@@ -135,6 +135,9 @@ constexpr int REDUCE_PARTS = 64;
 hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* partials, double* out,
                               hipStream_t s);
 
+// exhaustive order check of the hardware exp2 and reciprocal (out: 4 counters)
+hipError_t launch_check_monotone(unsigned long long* out, hipStream_t s);
+
 constexpr int TRAIN_BLOCK = 16 * 64;  // threads per workgroup of the per-tile training kernels
 hipError_t launch_swizzle(const float* params, int h, int C, int Cp, int nb, float* wimg, int64_t nw, float* wimgT,
                           int64_t nwT, hipStream_t s);

@@ -70,6 +70,17 @@ def test_cdf_rows_match_oracle(models, name):
     say(f"  entries off by 1: {(diff == 1).mean():.3e}, by >1: {(diff > 1).mean():.3e}")
 
 
+def test_hardware_exp2_rcp_monotone(nx):
+    """Every frequency >= 1 needs the CDF monotone in k: the exponent of
+    cdf_eval is monotone in k, so the hardware exp2 must be non-decreasing
+    and the reciprocal non-increasing. Checked over every finite FP32 value."""
+    say("[gpu] exhaustive monotonicity of exp2 / rcp")
+    r = nx.debug_check_monotone()
+    say(f"[gpu] {r}")
+    assert r["pairs"] == 2 * 0x7F800000 - 1
+    assert r["exp2_decreasing"] == 0 and r["rcp_increasing"] == 0 and r["sigmoid_increasing"] == 0
+
+
 @pytest.mark.parametrize("name", ["A", "B"])
 def test_nll_matches_oracle(models, name):
     say(f"[gpu] nll vs oracle, model {name}")
