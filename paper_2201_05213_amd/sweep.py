@@ -1,0 +1,111 @@
+"""Decode-time sweeps over model size and image size on one GPU: the serial
+raster decoder against the wavefront decoder (Sec. 3, Algorithm 1), whole
+image and with patches, in the manner of the paper's Table 2 (decode time
+per image for 0/1/3 residual blocks at 32x32, and for image sides 32 to
+1024 with no block). Inputs are seeded smooth synthetic images; models are
+random-init local models with h = 3.
+
+    python -m paper_2201_05213_amd.sweep > table.md
+"""
+from __future__ import annotations
+
+import argparse
+import sys
+
+import numpy as np
+import torch
+
+import paper_2201_05213_amd as nx
+
+__all__ = ["time_decode", "run"]
+
+
+def _images(n, H, W, seed):
+    """Seeded smooth fields (separable box-blurred noise, rescaled)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        z = rng.standard_normal((H + 8, W + 8, 3))
+        k = np.ones(5) / 5.0
+        z = np.apply_along_axis(lambda v: np.convolve(v, k, mode="same"), 0, z)
+        z = np.apply_along_axis(lambda v: np.convolve(v, k, mode="same"), 1, z)[4:4 + H, 4:4 + W]
+        z = (z - z.min()) / max(z.max() - z.min(), 1e-9) * 255.0
+        out.append(np.ascontiguousarray(np.clip(np.rint(z), 0, 255).astype(np.uint8)))
+    return out
+
+
+def time_decode(m, imgs, order, patch=None, interleave=1, reps=3):
+    """Median decode time (s) of the batch `imgs` (CUDA uint8 tensors),
+    decoding checked exact."""
+    data, offs = m.encode(imgs, order=order, patch=patch, interleave=interleave)
+    out = [torch.empty_like(t) for t in imgs]
+    plan, ws = m.decode_prepare(out, order=order, patch=patch, interleave=interleave)
+    status = torch.empty(len(imgs), dtype=torch.int32, device=m.device)
+    m.decode_run(plan, data, offs, status, ws)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(out, imgs)), "decode mismatch"
+    times = []
+    stream = torch.cuda.current_stream(m.device)
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        m.decode_run(plan, data, offs, status, ws)
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    return float(np.median(times))
+
+
+def _model(h, C, nb, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = 2 * h + 1
+    shapes = [C * 3 * K * K, C] + [C * C, C, C * C, C] * nb + [100 * C, 100]
+    fans = [3 * K * K, 3 * K * K] + [C] * (4 * nb) + [C, C]
+    parts = [rng.uniform(-1 / np.sqrt(f), 1 / np.sqrt(f), size=n) for n, f in zip(shapes, fans)]
+    from .blob import blob_from_params
+
+    return nx.Model(blob_from_params((h, C, nb, 10), np.concatenate(parts).astype(np.float32)))
+
+
+def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pr = lambda s: print(s, file=out, flush=True)  # noqa: E731
+    pr(f"### Model size (h = 3, C = {C}), one 32x32 image, decode time per image")
+    pr("")
+    pr("| residual blocks | raster | wavefront | speedup |")
+    pr("|---|---|---|---|")
+    img32 = [torch.from_numpy(i).to(dev) for i in _images(1, 32, 32, 7)]
+    for nb in (0, 1, 3):
+        m = _model(3, C, nb, 100 + nb)
+        tr = time_decode(m, img32, nx.RASTER)
+        tw = time_decode(m, img32, nx.WAVEFRONT)
+        pr(f"| {nb} | {tr * 1e3:.2f} ms | {tw * 1e3:.2f} ms | {tr / tw:.1f}x |")
+    pr("")
+    pr(f"### Image size (h = 3, C = {C}, no block), decode time per image")
+    pr("")
+    pr("| side | raster | wavefront, whole image | speedup | wavefront + 64x64 patches, 4 streams | speedup |")
+    pr("|---|---|---|---|---|---|")
+    m = _model(3, C, 0, 100)
+    for side in (32, 64, 128, 1024):
+        img = [torch.from_numpy(i).to(dev) for i in _images(1, side, side, 11 + side)]
+        if side <= 128:
+            tr = time_decode(m, img, nx.RASTER)
+            rnote = ""
+        else:
+            # raster time is the same per pixel on every row: a strip of rows, scaled
+            strip = [img[0][:raster_rows].contiguous()]
+            tr = time_decode(m, strip, nx.RASTER, reps=1) * side / raster_rows
+            rnote = f" ({raster_rows}-row strip, scaled)"
+        tw = time_decode(m, img, nx.WAVEFRONT, reps=2 if side > 128 else 3)
+        tp = time_decode(m, img, nx.WAVEFRONT, patch=(64, 64), interleave=4) if side >= 64 else float("nan")
+        sp = f"{tp * 1e3:.2f} ms | {tr / tp:.0f}x" if side >= 64 else "n/a | n/a"
+        pr(f"| {side} | {tr * 1e3:.2f} ms{rnote} | {tw * 1e3:.2f} ms | {tr / tw:.1f}x | {sp} |")
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--raster-rows", type=int, default=8)
+    a = ap.parse_args()
+    run(a.channels, a.raster_rows)
