@@ -26,15 +26,33 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link the library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp", *SOURCES]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
     noise = "packed-fp32-ops"
-    err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l and l.strip())
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], "-c", "-I", os.path.join(ROOT, "include"),
+               "-o", obj, src]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    errors = []
+    for src, pr in procs:
+        out, _ = pr.communicate()
+        msg = "\n".join(l for l in out.splitlines() if noise not in l and l.strip())
+        if pr.returncode != 0:
+            errors.append(f"{os.path.basename(src)}:\n{msg}")
+        elif verbose and msg:
+            print(msg, file=sys.stderr)
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if verbose and err:
-        print(err, file=sys.stderr)
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -376,3 +376,31 @@ def test_large6_full_size_in_bench_configuration(models, nx):
     gap = (got - ideal) / ideal
     say(f"[gpu] large6: sampled lanes gap {gap * 100:.4f}%")
     assert gap <= 1e-3
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_corrupt_streams_detected(models, nx, K):
+    """Damage to any of a lane's K streams is reported (status 4), never a
+    wrong image with status 0."""
+    say(f"[gpu] corrupt containers, K={K}")
+    m, _, _ = models["A"]
+    img = synth.smooth_field_image(2.0, 3, 0, 40, 40, 6)
+    t = cuda(img)
+    data, offs = m.encode([t], order=1, patch=(20, 20), interleave=K)
+    d = data.cpu().numpy()
+    nl = int.from_bytes(bytes(d[28:32]), "little")
+    ends = np.frombuffer(bytes(d[32:32 + 4 * nl * K]), dtype="<u4").astype(np.int64)
+    pay = 32 + 4 * nl * K
+    for e in range(nl * K):  # a byte in the middle of every stream
+        lo = 0 if e == 0 else int(ends[e - 1])
+        mid = pay + (lo + int(ends[e])) // 2
+        bad = data.clone()
+        bad[mid] ^= 0x5A
+        out, st = m.decode(bad, offs, [(40, 40)], order=1, patch=(20, 20), interleave=K, sync=False)
+        torch.cuda.synchronize()
+        assert int(st[0]) == 4 or torch.equal(out[0], t), e
+    # truncated stream table entry: the last stream ends past the container
+    bad = data.clone()
+    bad[32 + 4 * (nl * K - 1)] ^= 0x7F
+    _, st = m.decode(bad, offs, [(40, 40)], order=1, patch=(20, 20), interleave=K, sync=False)
+    assert int(st[0]) == 4
