@@ -71,6 +71,12 @@ def lib():
         L.ox_lane_count.argtypes = [I, I, I, I]
         L.ox_log_bin.restype = D
         L.ox_log_bin.argtypes = [I, D, D]
+        L.ox_philox4x64.restype = None
+        L.ox_philox4x64.argtypes = [P, P, P]
+        L.ox_sample_slot.restype = ctypes.c_uint32
+        L.ox_sample_slot.argtypes = [ctypes.c_uint64, I, I, I, I]
+        L.ox_sample.restype = I
+        L.ox_sample.argtypes = [P, I, I, I, I, I, ctypes.c_uint64, P]
         _lib = L
     return _lib
 
@@ -177,6 +183,33 @@ class Model:
         if rc:
             raise OracleError(rc, "decode")
         return img
+
+
+    # -- sampling ---------------------------------------------------------
+    def sample(self, H: int, W: int, seed: int, order: int = 1, ph: int = 0, pw: int = 0,
+               offset: int | None = None) -> np.ndarray:
+        """Ancestral sample (H, W, 3) uint8: each symbol is the inverse
+        quantised CDF at its Philox slot (see sample_slots)."""
+        img = np.zeros((H, W, 3), dtype=np.uint8)
+        if offset is None:
+            offset = (self.h + 1) if order == 1 else 0
+        rc = lib().ox_sample(self._h, H, W, offset, ph, pw, seed, _ptr(img))
+        if rc:
+            raise OracleError(rc, "sample")
+        return img
+
+
+def philox4x64(ctr, key) -> np.ndarray:
+    """One Philox4x64-10 block: 4 uint64 from a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    o = np.zeros(4, dtype=np.uint64)
+    lib().ox_philox4x64(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def sample_slot(seed: int, W: int, y: int, x: int, c: int) -> int:
+    return int(lib().ox_sample_slot(seed, W, y, x, c))
 
 
 def rans_encode(start, freq) -> bytes:

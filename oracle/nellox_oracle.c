@@ -25,7 +25,11 @@
  *   - raster order (the sequential decoder of Sec. 2) and the topological
  *     (wavefront) order of Sec. 3 / Fig. 3: pixel (i,j) at step j + (h+1) i;
  *   - the patch scheme: an image is cut into patch_h x patch_w tiles anchored
- *     at (0,0), each coded as an independent image with its own stream.
+ *     at (0,0), each coded as an independent image with its own stream;
+ *   - ancestral sampling from the same model in the same orders (the parallel
+ *     generation Sec. 5 leaves to future work): each symbol is the inverse of
+ *     its quantised CDF at a 16-bit uniform slot drawn from the Philox4x64-10
+ *     counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
  * Every floating point quantity is double precision.
  */
 #include <math.h>
@@ -618,4 +622,77 @@ int ox_decode(const ox_model *m, const uint8_t *in, size_t len, int H, int W, in
               uint8_t *img) {
   if (!m || (order != 0 && order != 1)) return OX_E_ARG;
   return ox_decode_offset(m, in, len, H, W, order ? m->h + 1 : 0, ph, pw, img);
+}
+
+/* ---------------------------------------------------------------- sampling */
+
+/* Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit
+ * products; the key is bumped by the two Weyl constants between rounds. */
+void ox_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    unsigned __int128 p0 = (unsigned __int128)M0 * x0, p1 = (unsigned __int128)M1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0, hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The uniform slot of channel c of pixel (y, x) of an H x W image (absolute
+ * coordinates): the top 16 bits of word c of the Philox block with counter
+ * (y W + x, 0, 0, 0) and key (seed, 0). */
+uint32_t ox_sample_slot(uint64_t seed, int W, int y, int x, int c) {
+  uint64_t ctr[4] = {(uint64_t)y * (uint64_t)W + (uint64_t)x, 0, 0, 0}, key[2] = {seed, 0}, o[4];
+  ox_philox4x64(ctr, key, o);
+  return (uint32_t)(o[c] >> 48);
+}
+
+/* Ancestral sampling of one lane in the decoding order of `offset`: per
+ * symbol, the CDF row given what is already drawn, then the unique v with
+ * cdf[v] <= slot < cdf[v + 1]; P(v) = freq_v / 2^16. */
+static int ox_sample_lane(const ox_model *m, ox_rect r, int offset, uint64_t seed, uint8_t *img, int W_img) {
+  long n = (long)r.h * r.w;
+  double *cv = (double *)malloc(sizeof(double) * 3 * n);
+  for (long k = 0; k < 3 * n; ++k) cv[k] = NAN;
+  ox_px *pxs = (ox_px *)malloc(sizeof(ox_px) * n);
+  int *seq = (int *)malloc(sizeof(int) * 3 * 3 * n);
+  long N = ox_symbol_order(r.h, r.w, offset, seq);
+  int rc = OX_OK;
+  int32_t cdf[257];
+  double mu[OX_NMIX];
+  for (long k = 0; k < N && !rc; ++k) {
+    int y = seq[3 * k], x = seq[3 * k + 1], c = seq[3 * k + 2];
+    long pi = (long)y * r.w + x;
+    if (c == 0) { rc = ox_px_begin(m, cv, r.h, r.w, y, x, &pxs[pi]); if (rc) break; }
+    rc = ox_px_cdf(&pxs[pi], c, cdf, mu);
+    if (rc) break;
+    uint32_t slot = ox_sample_slot(seed, W_img, r.y0 + y, r.x0 + x, c);
+    int v = 0;
+    while (v < 255 && (uint32_t)cdf[v + 1] <= slot) ++v;
+    ox_px_commit(&pxs[pi], c, mu, v);
+    cv[pi * 3 + c] = ox_normalise(v);
+    img[(((long)(r.y0 + y)) * W_img + r.x0 + x) * 3 + c] = (uint8_t)v;
+  }
+  free(cv); free(pxs); free(seq);
+  return rc;
+}
+
+/* Sample an H x W image (patches of ph x pw sampled independently, as they
+ * are coded) in the order of `offset` (0 raster, h + 1 wavefront). */
+int ox_sample(const ox_model *m, int H, int W, int offset, int ph, int pw, uint64_t seed, uint8_t *img) {
+  if (!m || !img || H < 1 || W < 1 || offset < 0) return OX_E_ARG;
+  int nl = ox_lane_count(H, W, ph, pw);
+  ox_rect *r = (ox_rect *)malloc(sizeof(ox_rect) * nl);
+  ox_lanes(H, W, ph, pw, r);
+  int rc = OX_OK;
+  for (int l = 0; l < nl && !rc; ++l) rc = ox_sample_lane(m, r[l], offset, seed, img, W);
+  free(r);
+  return rc;
 }

@@ -20,4 +20,5 @@ from .weights import (  # noqa: F401
     write_blob,
     fnv1a64,
     model_blob,
+    delta_params,
 )

@@ -81,3 +81,18 @@ def model_blob(name: str) -> tuple[bytes, dict]:
     d = MODEL_DIMS[name]
     p = init_params(d["h"], d["C"], d["n_blocks"], d["seed"])
     return write_blob(d["h"], d["C"], d["n_blocks"], p), dict(d)
+
+
+def delta_params(h: int, C: int, means=(-100.0, 100.0, -100.0)) -> np.ndarray:
+    """A model with no blocks whose every conditional is the same mixture: all
+    weights zero; the head bias gives component 0 logit 100 (the others 0),
+    mean means[c] to every component of channel c, log-scale -7 and zero
+    coefficients. A mean far below -1 puts all of F's mass into bin 0 (and
+    far above 1 into bin 255), so the quantised CDF is known in closed form."""
+    p = np.zeros(param_count(h, C, 0), dtype=np.float32)
+    hb = p[-100:]
+    hb[0] = 100.0
+    for c in range(3):
+        hb[10 + 10 * c:20 + 10 * c] = means[c]
+        hb[40 + 10 * c:50 + 10 * c] = -7.0
+    return p
