@@ -194,6 +194,34 @@ def main():
         f"{pass_step * 1e3:.2f} ms, {enc_rec['pass_tflops']:.1f} TFLOP/s ({enc_rec['pass_frac_fp32_peak'] * 100:.1f}% "
         f"of FP32 peak)")
 
+    # ancestral sampling of the same batch shape with the decoder's schedule
+    # (each symbol the inverse quantised CDF at a Philox slot; no coder)
+    smp_out = [torch.empty_like(t) for t in ts]
+    smp_arr = nx._images(smp_out)
+    seeds = (ctypes.c_uint64 * len(ts))(*[1000 + k for k in range(len(ts))])
+
+    def sample_once():
+        rc = L.nellox_sample(m._h, len(ts), seeds, ctypes.byref(o1), smp_arr, enc_ws.data_ptr(), enc_ws.numel(),
+                             ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"nellox_sample returned {rc}")
+
+    for _ in range(2):
+        sample_once()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(nrep):
+        sample_once()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    smp_step = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
+    smp_rec = {"px_per_s": npx / smp_step, "ms": smp_step * 1e3,
+               "tflops": flops_per_px * npx / smp_step / 1e12,
+               "frac_fp32_peak": flops_per_px * npx / smp_step / PEAK_FP32,
+               "sample": "the decode batch's shapes, wavefront order, same patches; one seed per image"}
+    log(f"[bench] sampling {smp_step * 1e3:.2f} ms ({npx / smp_step / 1e6:.0f} Mpx/s, "
+        f"{smp_rec['frac_fp32_peak'] * 100:.1f}% of FP32 peak)")
+
     # one 1024x1024 image alone: wavefront+patch latency
     one = [ts[0]]
     d1, o1 = m.encode(one, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave)
@@ -343,6 +371,7 @@ def main():
         "batch_px_per_s_vs_raster": value / raster_pxs,
         "encode_s_untimed": enc_s,
         "encode": enc_rec,
+        "sampling": smp_rec,
         "bits_per_dim": bpd,
         "gap_vs_oracle_ideal": gap,
         "roofline": {"bound": "mfma", "kernel": f"k_decode<{dims['h']},{dims['C']}>",

@@ -156,6 +156,25 @@ nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nell
 nellox_status nellox_decode_run(const nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
                                 const uint64_t* in_offsets, int32_t* status, void* ws, void* stream);
 
+/* ---- sampling (the O(D) parallel generation that Sec. 5 leaves to future
+ * work, run by the wavefront schedule of Sec. 3) ----
+ * Draws n images from the model into the preallocated out[k] (H, W set by the
+ * caller) by ancestral sampling. The symbol of channel c of pixel (y, x) of
+ * image k is the v with cdf[v] <= u < cdf[v + 1]: cdf is the quantised CDF
+ * row the coder uses given the pixels already drawn, u is the top 16 bits of
+ * word c of the Philox4x64-10 block (Salmon, Moraes, Dror, Shaw, SC'11) with
+ * counter (y W + x, 0, 0, 0) and key (seeds[k], 0). So P(v) = freq_v / 2^16
+ * exactly, and an image depends on its seed, size and patch shape only (not
+ * on the order, the batch or the launch). opts: order 0 raster or 1 wavefront
+ * (H + (h + 1)(W - 1) steps per patch instead of H W); patch_* cut the image
+ * into patches drawn independently, as the coder models them; interleave is
+ * ignored. seeds: host array of n values. ws: device workspace, at least
+ * nellox_workspace_bytes(m, n, out, opts) bytes (the plan is copied into it
+ * on `stream`). Errors: NELLOX_E_ARG (null pointer, bad size or order),
+ * NELLOX_E_CAPACITY (workspace), NELLOX_E_HIP (a launch failed). */
+nellox_status nellox_sample(const nellox_model* m, int32_t n, const uint64_t* seeds, const nellox_opts* opts,
+                            const nellox_image* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Continuous code length -log2 p(x) of each image under the model (Eq. 2's
  * objective): bits_per_px (nullable, device, sum of H*W floats) and
  * bits_total (device, n doubles). opts.patch_* selects the patch grid. */

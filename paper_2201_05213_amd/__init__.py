@@ -160,6 +160,25 @@ class Model:
         check(load().nellox_decode_run(self._h, ctypes.byref(plan), data.data_ptr(), offsets.data_ptr(),
                                        status.data_ptr(), ws.data_ptr(), _stream(self.device)), "nellox_decode_run")
 
+    def sample(self, shapes, seeds, order: int = WAVEFRONT, patch=None, out: Sequence[torch.Tensor] | None = None,
+               ws: torch.Tensor | None = None):
+        """Draw one image per (H, W) in `shapes` (uint8 H x W x 3 on the
+        model's device) by ancestral sampling; image k is a function of
+        seeds[k] (a 64-bit integer), its size and the patch shape only."""
+        L = load()
+        n = len(shapes)
+        if len(seeds) != n:
+            raise ValueError("one seed per image")
+        o = _opts(order, patch)
+        imgs = _shape_images(shapes, self.device) if out is None else list(out)
+        arr = _images(imgs)
+        sd = (ctypes.c_uint64 * max(n, 1))(*[int(v) & 0xFFFFFFFFFFFFFFFF for v in seeds])
+        if ws is None:
+            ws = self.workspace(arr, n, o)
+        check(L.nellox_sample(self._h, n, sd, ctypes.byref(o), arr, ws.data_ptr(), ws.numel(), _stream(self.device)),
+              "nellox_sample")
+        return imgs
+
     def nll(self, imgs: Sequence[torch.Tensor], patch=None, per_pixel: bool = False):
         """Continuous code length -log2 p(x) per image (float64 CUDA tensor)."""
         L = load()

@@ -43,6 +43,7 @@ SIGNATURES = {
     "nellox_decode_trace": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_decode_prepare": (_ST, [_P, _I32, _P, _P, _P, _SZ, _P, _P]),
     "nellox_decode_run": (_ST, [_P, _P, _P, _P, _P, _P, _P]),
+    "nellox_sample": (_ST, [_P, _I32, _P, _P, _P, _P, _SZ, _P]),
     "nellox_nll": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_symbols": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_cdf": (_ST, [_P, _P, _P, _P, _P, _SZ, _P]),

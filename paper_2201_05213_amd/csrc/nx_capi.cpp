@@ -562,6 +562,50 @@ nellox_status nellox_decode_trace(const nellox_model* m, int32_t n, const uint8_
   return decode_impl(m, n, in, in_offsets, o, out, status, dump, ws, ws_bytes, stream);
 }
 
+nellox_status nellox_sample(const nellox_model* mc, int32_t n, const uint64_t* seeds, const nellox_opts* o,
+                            const nellox_image* out, void* ws, size_t ws_bytes, void* stream) {
+  nellox_model* m = const_cast<nellox_model*>(mc);
+  if (check_model(m)) return NELLOX_E_ARG;
+  if (n > 0 && !seeds) return fail(NELLOX_E_ARG, "seeds is null");
+  if (!o) return fail(NELLOX_E_ARG, "opts is null");
+  nellox_opts so = *o;
+  so.interleave = 1;  // no streams when sampling
+  Plan P;
+  nellox_status st = make_plan(n, out, &so, P, true);
+  if (st) return st;
+  if (n == 0) return NELLOX_OK;
+  if (!ws) return fail(NELLOX_E_ARG, "null workspace");
+  const WsLayout W = ws_layout(P, n);
+  if ((int64_t)ws_bytes < W.img_bytes) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  for (int k = 0; k < n; ++k) P.d[k].seed = seeds[k];
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* w8 = (uint8_t*)ws;
+  hipError_t e = prepare_decode(m->h, m->Cp, 4);
+  if (e != hipSuccess) return hip_fail(e, "sampler set-up");
+  if ((st = upload_plan(m, P, w8, W, s))) return st;
+  int32_t* counter = (int32_t*)(w8 + W.flags + 4);
+  e = launch_decode_prep(nullptr, 0, counter, s);
+  if (e != hipSuccess) return hip_fail(e, "sampler prep launch");
+  DecArgs a{};
+  a.w = m->dw;
+  a.wfloats = m->wfloats;
+  a.nb = m->nb;
+  a.desc = (const ImgDesc*)(w8 + W.desc);
+  a.n_img = n;
+  a.n_lanes = P.n_lanes;
+  a.order = o->order;
+  a.K = 4;
+  a.model_hash = m->hash;
+  a.counter = counter;
+  // the decoder's launch shape: lanes spread over every CU
+  const int cus = persistent_grid(m);
+  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
+  const int grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
+  e = launch_sample(m->h, m->Cp, a, grid, waves, s);
+  if (e != hipSuccess) return hip_fail(e, "sampler launch");
+  return NELLOX_OK;
+}
+
 nellox_status nellox_nll(const nellox_model* mc, int32_t n, const nellox_image* imgs, const nellox_opts* o,
                          float* bits_per_px, double* bits_total, void* ws, size_t ws_bytes, void* stream) {
   nellox_model* m = const_cast<nellox_model*>(mc);

@@ -424,4 +424,37 @@ NXD float posterior(Mix& M, int x, const float (&mu)[3], const float (&is)[3], b
   return lse;
 }
 
+// ------------------------------------------------------------------ sampling
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): a counter-based
+// generator of ten rounds; each round multiplies words 0 and 2 by two odd
+// constants (full 128-bit products) and mixes the halves with words 1 and 3
+// and the key, which steps by two Weyl increments between rounds. Here the
+// counter is (n, 0, 0, 0) and the key (seed, 0).
+NXD void philox4x64(uint64_t n, uint64_t seed, uint64_t (&o)[4]) {
+  uint64_t x0 = n, x1 = 0, x2 = 0, x3 = 0, k0 = seed, k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t a = 0xD2E7470EE14C6C93ull, b = 0xCA5A826395121157ull;
+    const uint64_t hi0 = __umul64hi(a, x0), lo0 = a * x0;
+    const uint64_t hi1 = __umul64hi(b, x2), lo1 = b * x2;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += 0x9E3779B97F4A7C15ull;
+    k1 += 0xBB67AE8584CAA73Bull;
+  }
+  o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
+// the 16-bit uniform slots of the three channels of pixel (y, x) of a W-wide
+// image: top 16 bits of words 0, 1, 2 of the block with counter y W + x
+NXD void sample_slots(uint64_t seed, int W, int y, int x, uint32_t (&sl)[3]) {
+  uint64_t o[4];
+  philox4x64((uint64_t)y * (uint64_t)W + (uint64_t)x, seed, o);
+  sl[0] = (uint32_t)(o[0] >> 48);
+  sl[1] = (uint32_t)(o[1] >> 48);
+  sl[2] = (uint32_t)(o[2] >> 48);
+}
+
 }  // namespace nx

@@ -75,6 +75,7 @@ NXD ImgDesc uniform_desc(const ImgDesc* __restrict__ p) {
   D.tile_base = uniform64(D.tile_base);
   D.ntx = uniform(D.ntx);
   D.slot_base = uniform64(D.slot_base);
+  D.seed = (uint64_t)uniform64((int64_t)D.seed);
   return D;
 }
 
@@ -431,8 +432,11 @@ struct RowStream {
 
 // K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
 // streams k) per iteration, their searches independent of each other.
-template <int H_, int C_, bool TRACE, int K>
+// SAMPLE: ancestral sampling instead of decoding (K = 4 structure, no
+// container): each symbol is the inverse quantised CDF at its Philox slot.
+template <int H_, int C_, bool TRACE, int K, bool SAMPLE>
 __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int64_t L, int lane) {
+  static_assert(!SAMPLE || K == 4, "sampling runs the four-row structure");
   const int p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
   const int n = find_img_uniform(A.desc, A.n_img, L);
@@ -442,13 +446,17 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   const int ly = q / D.nlx, lx = q - ly * D.nlx;
   const int y0 = ly * D.ph, x0 = lx * D.pw;
   const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
-  const uint8_t* C = A.in + uniform64((int64_t)A.in_off[n]);
-  const int64_t clen = uniform64((int64_t)(A.in_off[n + 1] - A.in_off[n]));
-  const int64_t pay = HDR_BYTES + 4 * (int64_t)nl * K;
+  const uint8_t* C = nullptr;
+  int64_t clen = 0, pay = 0;
   // header and stream table checks (every lane reads the same bytes; the
   // verdicts are made wave-uniform, and status is stored by every lane)
-  bool ok = clen >= pay;
+  bool ok = true;
   bool mismatch = false;
+  if constexpr (!SAMPLE) {
+  C = A.in + uniform64((int64_t)A.in_off[n]);
+  clen = uniform64((int64_t)(A.in_off[n + 1] - A.in_off[n]));
+  pay = HDR_BYTES + 4 * (int64_t)nl * K;
+  ok = clen >= pay;
   if (ok) {
     const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
     ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION &&
@@ -461,6 +469,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       mismatch = uniform(hsh != A.model_hash ? 1 : 0) != 0;
     }
   }
+  }  // !SAMPLE
   if (mismatch) {
     A.status[n] = ST_MISMATCH;
     return;
@@ -471,7 +480,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   ByteStage R[KS];
   uint32_t x[KS], pos[KS];
   RowStream RS;
-  if constexpr (K == 4) {
+  if constexpr (SAMPLE) {
+  } else if constexpr (K == 4) {
     const int64_t e = (int64_t)q * K + g;  // stream table entry of this row
     uint32_t lend = 0, lstart = 0;
     bool okr = ok;
@@ -501,7 +511,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     A.status[n] = ST_CORRUPT;
     return;
   }
-  if constexpr (K == 4) {
+  if constexpr (SAMPLE) {
+  } else if constexpr (K == 4) {
     RS.fill(0, p);
     RS.x = (uint32_t)__shfl((int)RS.word, g << 4);  // bytes 0..3, little endian
     RS.pos = 4;
@@ -537,6 +548,9 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       float ctx[conv_chunks(H_)];
       tc.refresh();
       gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
+      // sampling: the slots of pixel p (every lane group draws the same)
+      uint32_t sl[3] = {0u, 0u, 0u};
+      if constexpr (SAMPLE) sample_slots(D.seed, D.W, y0 + i, x0 + j, sl);
       f4 head[HEAD_TILES];
       net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
       Mix M;
@@ -586,7 +600,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             Mix10 P;
             load_mix10(P, prm, prc);
             const uint32_t pv = piv[prc * 16 + p];
-            const uint32_t slot = RS.x & 0xffffu;
+            const uint32_t slot = SAMPLE ? (uint32_t)__shfl((int)sl[c], prc) : RS.x & 0xffffu;
             const int b = row_count(__ballot(pv <= slot), g);
             const int k2 = 16 * b + p;
             const uint32_t c2 = cdf_quant(k2, cdf_eval10(max(k2, 1), P));
@@ -600,9 +614,11 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             const uint32_t lo = b == 0 ? 0u : lo_r;
             const uint32_t start = cnt == 0 ? lo : st_r;
             const uint32_t freq = (cnt < 15 ? nc_r : np_r) - start;
-            const uint32_t xn = freq * (RS.x >> 16) + slot - start;
-            RS.x = act ? xn : RS.x;
-            RS.renorm(act, p, g);
+            if constexpr (!SAMPLE) {
+              const uint32_t xn = freq * (RS.x >> 16) + slot - start;
+              RS.x = act ? xn : RS.x;
+              RS.renorm(act, p, g);
+            }
             // the symbol of pixel p (decoded by row p - q0) to all its lanes
             const int src = p - q0;
             const int sv = __shfl(sy, (src & 3) << 4);
@@ -729,7 +745,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     }
   }
   bool clean = true;
-  if constexpr (K == 4) {
+  if constexpr (SAMPLE) {
+  } else if constexpr (K == 4) {
     clean = __ballot(RS.x == RANS_X0 && RS.pos == RS.len) == ~0ull;
   } else {
 #pragma unroll
@@ -738,7 +755,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   if (!clean) A.status[n] = ST_CORRUPT;
 }
 
-template <int H_, int C_, bool TRACE, int K>
+template <int H_, int C_, bool TRACE, int K, bool SAMPLE>
 __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
@@ -752,13 +769,13 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
     if (lane == leader) L = atomicAdd(A.counter, 1);
     L = uniform(L);
     if ((int64_t)L >= A.n_lanes) break;
-    decode_lane<H_, C_, TRACE, K>(A, w, piv, L, lane);
+    decode_lane<H_, C_, TRACE, K, SAMPLE>(A, w, piv, L, lane);
   }
 }
 
 __global__ void k_decode_prep(int32_t* status, int n_img, int32_t* counter) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_img) status[i] = ST_OK;
+  if (status && i < n_img) status[i] = ST_OK;
   if (i == 0) *counter = 0;
 }
 
@@ -864,10 +881,10 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int H_, int C_, bool TRACE, int K>
+template <int H_, int C_, bool TRACE, int K, bool SAMPLE = false>
 static hipError_t decode_tt(const DecArgs& a, int grid, int waves, hipStream_t s) {
   const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * WAVE_LDS_WORDS * 4;
-  hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K>), dim3(grid), dim3(waves * 64), lds, s, a);
+  hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K, SAMPLE>), dim3(grid), dim3(waves * 64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -879,8 +896,9 @@ static hipError_t decode_setup_k() {
   int dev = 0, lim = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, K>, (size_t)lim);
-  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, true, K>, (size_t)lim);
+  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, K, false>, (size_t)lim);
+  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, true, K, false>, (size_t)lim);
+  if (K == 4 && e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, 4, true>, (size_t)lim);
   return e;
 }
 
@@ -894,6 +912,11 @@ static hipError_t decode_setup(int K) {
 template <int H_, int C_, int K>
 static hipError_t decode_k(const DecArgs& a, int grid, int waves, hipStream_t s) {
   return a.sym_dump ? decode_tt<H_, C_, true, K>(a, grid, waves, s) : decode_tt<H_, C_, false, K>(a, grid, waves, s);
+}
+
+template <int H_, int C_>
+static hipError_t sample_t(const DecArgs& a, int grid, int waves, hipStream_t s) {
+  return decode_tt<H_, C_, false, 4, true>(a, grid, waves, s);
 }
 
 template <int H_, int C_>
@@ -927,6 +950,12 @@ hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hi
   if (a.n_lanes == 0) return hipSuccess;
   if (waves < 1 || waves > NWAVES_DEC) return hipErrorInvalidValue;
   NX_DISPATCH(decode_t, h, C, a, grid, waves, s);
+}
+
+hipError_t launch_sample(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s) {
+  if (a.n_lanes == 0) return hipSuccess;
+  if (waves < 1 || waves > NWAVES_DEC) return hipErrorInvalidValue;
+  NX_DISPATCH(sample_t, h, C, a, grid, waves, s);
 }
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {

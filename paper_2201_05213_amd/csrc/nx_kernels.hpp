@@ -129,6 +129,9 @@ hipError_t prepare_decode(int h, int C, int K);
 // waves per workgroup in 1..DECODE_WAVES (the LDS takes one pivot table per wave);
 // prepare_decode must have run for (h, C, a.K)
 hipError_t launch_decode(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s);
+// ancestral sampling with the decoder's schedule (DecArgs: in, in_off, status
+// and sym_dump unused; every image descriptor carries its seed)
+hipError_t launch_sample(int h, int C, const DecArgs& a, int grid, int waves, hipStream_t s);
 // per-image FP64 sums of per-pixel bits, in a fixed order (partials: n_img
 // x REDUCE_PARTS doubles of scratch)
 constexpr int REDUCE_PARTS = 64;

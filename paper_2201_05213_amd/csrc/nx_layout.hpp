@@ -60,8 +60,9 @@ struct ImgDesc {
   int32_t ntx;         // encode tiles per image row = ceil(W/16)
   int32_t pad_;
   int64_t slot_base;   // byte offset of this image's first rANS lane slot
+  uint64_t seed;       // sampling: key word 0 of the image's Philox stream
 };
-static_assert(sizeof(ImgDesc) == 72, "descriptor layout");
+static_assert(sizeof(ImgDesc) == 80, "descriptor layout");
 
 // Container header (little endian), followed by u32 end[n_lanes * K]
 // (cumulative payload bytes per stream, stream k of lane q at q K + k) and

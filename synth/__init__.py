@@ -8,6 +8,7 @@ implementation can lean on the other through it.
 from .images import (  # noqa: F401
     smooth_field_image,
     workload_images,
+    workload_shapes,
     WORKLOADS,
     training_pool,
     training_crops,
