@@ -71,6 +71,18 @@ def lib():
         L.ox_lane_count.argtypes = [I, I, I, I]
         L.ox_log_bin.restype = D
         L.ox_log_bin.argtypes = [I, D, D]
+        L.ox_shear.restype = None
+        L.ox_shear.argtypes = [P, I, I, I, I, P]
+        L.ox_unshear.restype = None
+        L.ox_unshear.argtypes = [P, I, I, I, I, P]
+        L.ox_shear_tap_live.restype = I
+        L.ox_shear_tap_live.argtypes = [I, I, I]
+        L.ox_shear_kernel.restype = None
+        L.ox_shear_kernel.argtypes = [P, P]
+        L.ox_theta_image_shear.restype = I
+        L.ox_theta_image_shear.argtypes = [P, P, I, I, P]
+        L.ox_decode_shear.restype = I
+        L.ox_decode_shear.argtypes = [P, P, S, I, I, I, I, P]
         L.ox_philox4x64.restype = None
         L.ox_philox4x64.argtypes = [P, P, P]
         L.ox_sample_slot.restype = ctypes.c_uint32
@@ -185,6 +197,32 @@ class Model:
         return img
 
 
+    # -- ShearLoC (Sec. 3.1, Algorithm 2) -----------------------------------
+    def shear_kernel(self) -> np.ndarray:
+        """The sheared first kernel, (C, 3, h+1, h(h+2))."""
+        h = self.h
+        Kp = np.zeros((self.C, 3, h + 1, h * (h + 2)), dtype=np.float64)
+        lib().ox_shear_kernel(self._h, _ptr(Kp))
+        return Kp
+
+    def theta_image_shear(self, img: np.ndarray) -> np.ndarray:
+        img = np.ascontiguousarray(img, dtype=np.uint8)
+        H, W, _ = img.shape
+        th = np.zeros((H, W, 100), dtype=np.float64)
+        rc = lib().ox_theta_image_shear(self._h, _ptr(img), H, W, _ptr(th))
+        if rc:
+            raise OracleError(rc, "theta_shear")
+        return th
+
+    def decode_shear(self, data: bytes, H: int, W: int, ph: int = 0, pw: int = 0) -> np.ndarray:
+        """Decode a wavefront-order container with the sheared model."""
+        buf = np.frombuffer(data, dtype=np.uint8).copy()
+        img = np.zeros((H, W, 3), dtype=np.uint8)
+        rc = lib().ox_decode_shear(self._h, _ptr(buf), buf.size, H, W, ph, pw, _ptr(img))
+        if rc:
+            raise OracleError(rc, "decode_shear")
+        return img
+
     # -- sampling ---------------------------------------------------------
     def sample(self, H: int, W: int, seed: int, order: int = 1, ph: int = 0, pw: int = 0,
                offset: int | None = None) -> np.ndarray:
@@ -197,6 +235,33 @@ class Model:
         if rc:
             raise OracleError(rc, "sample")
         return img
+
+
+def shear(x: np.ndarray, o: int) -> np.ndarray:
+    """(H, W[, nc]) -> (H, W + o (H - 1)[, nc]) sheared with offset o."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    squeeze = a.ndim == 2
+    if squeeze:
+        a = a[:, :, None]
+    H, W, nc = a.shape
+    S = np.zeros((H, W + o * (H - 1), nc), dtype=np.float64)
+    lib().ox_shear(_ptr(a), H, W, nc, o, _ptr(S))
+    return S[:, :, 0] if squeeze else S
+
+
+def unshear(S: np.ndarray, W: int, o: int) -> np.ndarray:
+    a = np.ascontiguousarray(S, dtype=np.float64)
+    squeeze = a.ndim == 2
+    if squeeze:
+        a = a[:, :, None]
+    H, _, nc = a.shape
+    x = np.zeros((H, W, nc), dtype=np.float64)
+    lib().ox_unshear(_ptr(a), H, W, nc, o, _ptr(x))
+    return x[:, :, 0] if squeeze else x
+
+
+def shear_tap_live(h: int, a: int, q: int) -> bool:
+    return bool(lib().ox_shear_tap_live(h, a, q))
 
 
 def philox4x64(ctr, key) -> np.ndarray:

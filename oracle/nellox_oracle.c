@@ -26,6 +26,9 @@
  *     (wavefront) order of Sec. 3 / Fig. 3: pixel (i,j) at step j + (h+1) i;
  *   - the patch scheme: an image is cut into patch_h x patch_w tiles anchored
  *     at (0,0), each coded as an independent image with its own stream;
+ *   - the sheared model of Sec. 3.1 (ShearLoC, Algorithm 2): image and first
+ *     kernel sheared with offset o = h + 1 (Fig. 4b, Fig. 5b/5d), so that one
+ *     wavefront step is one column; decoding column by column, then unshear;
  *   - ancestral sampling from the same model in the same orders (the parallel
  *     generation Sec. 5 leaves to future work): each symbol is the inverse of
  *     its quantised CDF at a 16-bit uniform slot drawn from the Philox4x64-10
@@ -137,25 +140,11 @@ int ox_tap_live(int h, int dy, int dx) { return dy < h || (dy == h && dx < h); }
 
 static double ox_elu(double x) { return x > 0.0 ? x : expm1(x); }
 
-/* Pre-activation logits theta[100] of pixel (i,j) of a canvas of normalised
- * values (H x W x 3, NaN where not yet decoded). Positions outside the canvas
- * read as zero (the padding of Eq. 3). Returns OX_E_NAN if a NaN was read. */
-static int ox_theta(const ox_model *m, const double *cv, int H, int W, int i, int j, double *theta) {
-  const int h = m->h, K = m->K, C = m->C;
-  double a[C], u[C], z[C];
-  int nan_seen = 0;
-  for (int c = 0; c < C; ++c) a[c] = m->conv_b[c];
-  for (int dy = 0; dy < K; ++dy)
-    for (int dx = 0; dx < K; ++dx) {
-      if (!ox_tap_live(h, dy, dx)) continue;
-      int y = i - h + dy, x = j - h + dx;
-      if (y < 0 || y >= H || x < 0 || x >= W) continue; /* zero padding */
-      for (int ch = 0; ch < 3; ++ch) {
-        double v = cv[((long)y * W + x) * 3 + ch];
-        if (isnan(v)) nan_seen = 1;
-        for (int c = 0; c < C; ++c) a[c] += m->conv_w[(((long)c * 3 + ch) * K + dy) * K + dx] * v;
-      }
-    }
+/* Everything after the first layer (Sec. 2.1: 1x1 layers only): residual
+ * blocks on the first layer's output a[C], then the head into theta[100]. */
+static void ox_body(const ox_model *m, double *a, double *theta) {
+  const int C = m->C;
+  double u[C], z[C];
   for (int b = 0; b < m->nb; ++b) {
     for (int c = 0; c < C; ++c) u[c] = ox_elu(a[c]);
     for (int o = 0; o < C; ++o) {
@@ -176,6 +165,28 @@ static int ox_theta(const ox_model *m, const double *cv, int H, int W, int i, in
     for (int c = 0; c < C; ++c) s += m->head_w[(long)o * C + c] * u[c];
     theta[o] = s;
   }
+}
+
+/* Pre-activation logits theta[100] of pixel (i,j) of a canvas of normalised
+ * values (H x W x 3, NaN where not yet decoded). Positions outside the canvas
+ * read as zero (the padding of Eq. 3). Returns OX_E_NAN if a NaN was read. */
+static int ox_theta(const ox_model *m, const double *cv, int H, int W, int i, int j, double *theta) {
+  const int h = m->h, K = m->K, C = m->C;
+  double a[C];
+  int nan_seen = 0;
+  for (int c = 0; c < C; ++c) a[c] = m->conv_b[c];
+  for (int dy = 0; dy < K; ++dy)
+    for (int dx = 0; dx < K; ++dx) {
+      if (!ox_tap_live(h, dy, dx)) continue;
+      int y = i - h + dy, x = j - h + dx;
+      if (y < 0 || y >= H || x < 0 || x >= W) continue; /* zero padding */
+      for (int ch = 0; ch < 3; ++ch) {
+        double v = cv[((long)y * W + x) * 3 + ch];
+        if (isnan(v)) nan_seen = 1;
+        for (int c = 0; c < C; ++c) a[c] += m->conv_w[(((long)c * 3 + ch) * K + dy) * K + dx] * v;
+      }
+    }
+  ox_body(m, a, theta);
   return nan_seen ? OX_E_NAN : OX_OK;
 }
 
@@ -694,5 +705,170 @@ int ox_sample(const ox_model *m, int H, int W, int offset, int ph, int pw, uint6
   int rc = OX_OK;
   for (int l = 0; l < nl && !rc; ++l) rc = ox_sample_lane(m, r[l], offset, seed, img, W);
   free(r);
+  return rc;
+}
+
+/* ---------------------------------------------------------------- ShearLoC */
+
+/* Shear (Sec. 3.1, Fig. 4b) an H x W x nc array with offset o into H x L x nc,
+ * L = W + o (H - 1): element (i, j) goes to column j + o i; the rest is 0. */
+void ox_shear(const double *x, int H, int W, int nc, int o, double *S) {
+  long L = (long)W + (long)o * (H - 1);
+  for (long k = 0; k < (long)H * L * nc; ++k) S[k] = 0.0;
+  for (int i = 0; i < H; ++i)
+    for (int j = 0; j < W; ++j)
+      for (int c = 0; c < nc; ++c) S[((long)i * L + j + (long)o * i) * nc + c] = x[((long)i * W + j) * nc + c];
+}
+
+/* Undo the shear: x(i, j) = S(i, j + o i). */
+void ox_unshear(const double *S, int H, int W, int nc, int o, double *x) {
+  long L = (long)W + (long)o * (H - 1);
+  for (int i = 0; i < H; ++i)
+    for (int j = 0; j < W; ++j)
+      for (int c = 0; c < nc; ++c) x[((long)i * W + j) * nc + c] = S[((long)i * L + j + (long)o * i) * nc + c];
+}
+
+/* The sheared first kernel (Sec. 3.1, Fig. 5b/5d): (h+1) rows by Q = h(h+2)
+ * columns. Row a of the unsheared causal kernel moves right by o a
+ * (o = h + 1); kernel column q then reads sheared column t - Q + q of the
+ * pixel's own column t, so only earlier columns are read. */
+int ox_shear_tap_live(int h, int a, int q) {
+  int dx = q - (h + 1) * a;
+  return a >= 0 && a <= h && dx >= 0 && dx <= 2 * h && ox_tap_live(h, a, dx);
+}
+
+/* Kp[c][ch][a][q] (C x 3 x (h+1) x h(h+2)) from the model's first kernel. */
+void ox_shear_kernel(const ox_model *m, double *Kp) {
+  const int h = m->h, K = m->K, C = m->C, Q = h * (h + 2);
+  for (int c = 0; c < C; ++c)
+    for (int ch = 0; ch < 3; ++ch)
+      for (int a = 0; a <= h; ++a)
+        for (int q = 0; q < Q; ++q) {
+          double w = 0.0;
+          if (ox_shear_tap_live(h, a, q)) w = m->conv_w[(((long)c * 3 + ch) * K + a) * K + (q - (h + 1) * a)];
+          Kp[(((long)c * 3 + ch) * (h + 1) + a) * Q + q] = w;
+        }
+}
+
+/* theta[100] of the pixel at row i, sheared column t, of a sheared canvas S
+ * (H x L x 3, NaN where not decoded yet, 0 off the image): the sheared
+ * kernel over columns t - Q .. t - 1 of rows i - h .. i (rows above the
+ * image read 0), then the unchanged 1x1 layers. The live taps are visited
+ * in the order of the unsheared kernel. */
+static int ox_theta_sheared(const ox_model *m, const double *Kp, const double *S, int H, long L, int i, long t,
+                            double *theta) {
+  const int h = m->h, C = m->C, Q = h * (h + 2);
+  double a[C];
+  int nan_seen = 0;
+  (void)H;
+  for (int c = 0; c < C; ++c) a[c] = m->conv_b[c];
+  for (int ka = 0; ka <= h; ++ka)
+    for (int q = 0; q < Q; ++q) {
+      if (!ox_shear_tap_live(h, ka, q)) continue;
+      int r = i - h + ka;
+      long tau = t - Q + q;
+      if (r < 0 || tau < 0) continue; /* above the image / left of column 0 */
+      for (int ch = 0; ch < 3; ++ch) {
+        double v = S[((long)r * L + tau) * 3 + ch];
+        if (isnan(v)) nan_seen = 1;
+        for (int c = 0; c < C; ++c) a[c] += Kp[(((long)c * 3 + ch) * (h + 1) + ka) * Q + q] * v;
+      }
+    }
+  ox_body(m, a, theta);
+  return nan_seen ? OX_E_NAN : OX_OK;
+}
+
+/* theta of every pixel of a complete image, computed in the sheared model. */
+int ox_theta_image_shear(const ox_model *m, const uint8_t *img, int H, int W, double *theta) {
+  const int o = m->h + 1;
+  long L = (long)W + (long)o * (H - 1), n = (long)H * W;
+  double *cv = (double *)malloc(sizeof(double) * 3 * n);
+  double *S = (double *)malloc(sizeof(double) * 3 * (size_t)H * L);
+  double *Kp = (double *)malloc(sizeof(double) * (size_t)m->C * 3 * (m->h + 1) * m->h * (m->h + 2));
+  for (long k = 0; k < 3 * n; ++k) cv[k] = ox_normalise(img[k]);
+  ox_shear(cv, H, W, 3, o, S);
+  ox_shear_kernel(m, Kp);
+  int rc = OX_OK;
+  for (int i = 0; i < H && !rc; ++i)
+    for (int j = 0; j < W && !rc; ++j)
+      rc = ox_theta_sheared(m, Kp, S, H, L, i, j + (long)o * i, theta + ((long)i * W + j) * OX_NOUT);
+  free(cv); free(S); free(Kp);
+  return rc;
+}
+
+/* Algorithm 2 on one lane: the canvas is kept sheared (NaN at every pixel not
+ * decoded yet, 0 elsewhere); column t = 0 .. L-1 holds exactly the pixels of
+ * wavefront step t, decoded in the coder's order from their predictive
+ * distributions; the sheared byte canvas is unsheared at the end. */
+static int ox_decode_lane_shear(const ox_model *m, const double *Kp, const uint8_t *in, size_t len, ox_rect r,
+                                uint8_t *img, int W_img) {
+  const int o = m->h + 1, H = r.h, W = r.w;
+  long L = (long)W + (long)o * (H - 1), n = (long)H * W;
+  double *nanimg = (double *)malloc(sizeof(double) * 3 * n);
+  double *S = (double *)malloc(sizeof(double) * 3 * (size_t)H * L);
+  double *Sb = (double *)malloc(sizeof(double) * 3 * (size_t)H * L);
+  double *out = (double *)malloc(sizeof(double) * 3 * n);
+  for (long k = 0; k < 3 * n; ++k) nanimg[k] = NAN;
+  ox_shear(nanimg, H, W, 3, o, S); /* poisoned pixels, zero padding */
+  for (long k = 0; k < 3 * (long)H * L; ++k) Sb[k] = 0.0;
+  ox_px *pxs = (ox_px *)malloc(sizeof(ox_px) * n);
+  int *seq = (int *)malloc(sizeof(int) * 3 * 3 * n);
+  long N = ox_symbol_order(H, W, o, seq);
+  ox_rdec d;
+  ox_rdec_init(&d, in, len);
+  int rc = d.bad ? OX_E_CORRUPT : OX_OK;
+  int32_t cdf[257];
+  double mu[OX_NMIX], th[OX_NOUT];
+  for (long k = 0; k < N && !rc; ++k) {
+    int i = seq[3 * k], j = seq[3 * k + 1], c = seq[3 * k + 2];
+    long t = j + (long)o * i, pi = (long)i * W + j;
+    if (c == 0) {
+      rc = ox_theta_sheared(m, Kp, S, H, L, i, t, th);
+      if (rc) break;
+      ox_mix_from_theta(th, &pxs[pi].mx);
+      memcpy(pxs[pi].logw, pxs[pi].mx.logw, sizeof(pxs[pi].logw));
+      pxs[pi].xt[0] = pxs[pi].xt[1] = pxs[pi].xt[2] = 0.0;
+    }
+    rc = ox_px_cdf(&pxs[pi], c, cdf, mu);
+    if (rc) break;
+    uint32_t slot = ox_rdec_slot(&d);
+    int v = 0;
+    while (v < 255 && (uint32_t)cdf[v + 1] <= slot) ++v;
+    ox_rdec_advance(&d, (uint32_t)cdf[v], (uint32_t)(cdf[v + 1] - cdf[v]));
+    ox_px_commit(&pxs[pi], c, mu, v);
+    S[((long)i * L + t) * 3 + c] = ox_normalise(v);
+    Sb[((long)i * L + t) * 3 + c] = (double)v;
+  }
+  if (!rc && !(d.x == 1u && d.pos == d.len)) rc = OX_E_CORRUPT;
+  if (!rc) {
+    ox_unshear(Sb, H, W, 3, o, out);
+    for (int i = 0; i < H; ++i)
+      for (int j = 0; j < W; ++j)
+        for (int c = 0; c < 3; ++c)
+          img[(((long)(r.y0 + i)) * W_img + r.x0 + j) * 3 + c] = (uint8_t)out[((long)i * W + j) * 3 + c];
+  }
+  free(nanimg); free(S); free(Sb); free(out); free(pxs); free(seq);
+  return rc;
+}
+
+/* Decode a wavefront-order container with the sheared model (Algorithm 2). */
+int ox_decode_shear(const ox_model *m, const uint8_t *in, size_t len, int H, int W, int ph, int pw, uint8_t *img) {
+  if (!m || !in || !img || H < 1 || W < 1) return OX_E_ARG;
+  int nl = ox_lane_count(H, W, ph, pw);
+  if (len < 4 || (int)rd32(in) != nl || len < 4 + 4 * (size_t)nl) return OX_E_CORRUPT;
+  ox_rect *r = (ox_rect *)malloc(sizeof(ox_rect) * nl);
+  ox_lanes(H, W, ph, pw, r);
+  double *Kp = (double *)malloc(sizeof(double) * (size_t)m->C * 3 * (m->h + 1) * m->h * (m->h + 2));
+  ox_shear_kernel(m, Kp);
+  size_t pos = 4 + 4 * (size_t)nl;
+  int rc = OX_OK;
+  for (int l = 0; l < nl && !rc; ++l) {
+    size_t nb = rd32(in + 4 + 4 * l);
+    if (pos + nb > len) { rc = OX_E_CORRUPT; break; }
+    rc = ox_decode_lane_shear(m, Kp, in + pos, nb, r[l], img, W);
+    pos += nb;
+  }
+  if (!rc && pos != len) rc = OX_E_CORRUPT;
+  free(r); free(Kp);
   return rc;
 }
