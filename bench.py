@@ -194,6 +194,25 @@ def main():
         f"{pass_step * 1e3:.2f} ms, {enc_rec['pass_tflops']:.1f} TFLOP/s ({enc_rec['pass_frac_fp32_peak'] * 100:.1f}% "
         f"of FP32 peak)")
 
+    # the same containers decoded in the sheared layout (ShearLoC, Algorithm 2)
+    plan2, ws2 = m.decode_prepare(outs, order=nx.SHEARED, patch=patch, interleave=args.interleave)
+    for _ in range(2):
+        m.decode_run(plan2, data, offs, status, ws2)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(nrep):
+        m.decode_run(plan2, data, offs, status, ws2)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(outs, ts)), "sheared round trip failed"
+    assert int(status.abs().sum()) == 0
+    shear_step = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
+    shear_rec = {"px_per_s": npx / shear_step, "ms": shear_step * 1e3, "vs_wavefront": step_s / shear_step,
+                 "sample": "the timed containers decoded with order 2 (prepared run), round trip checked"}
+    log(f"[bench] sheared-layout decode {shear_step * 1e3:.2f} ms ({npx / shear_step / 1e6:.0f} Mpx/s, "
+        f"{step_s / shear_step:.3f}x the unsheared decoder)")
+    del ws2
+
     # ancestral sampling of the same batch shape with the decoder's schedule
     # (each symbol the inverse quantised CDF at a Philox slot; no coder)
     smp_out = [torch.empty_like(t) for t in ts]
@@ -372,6 +391,7 @@ def main():
         "encode_s_untimed": enc_s,
         "encode": enc_rec,
         "sampling": smp_rec,
+        "sheared_decode": shear_rec,
         "bits_per_dim": bpd,
         "gap_vs_oracle_ideal": gap,
         "roofline": {"bound": "mfma", "kernel": f"k_decode<{dims['h']},{dims['C']}>",

@@ -65,7 +65,11 @@ typedef enum {
 } nellox_status;
 
 typedef struct {
-  int32_t order;      /* 0 raster, 1 wavefront */
+  int32_t order;      /* 0 raster, 1 wavefront (Algorithm 1), 2 wavefront decoded in the
+                         sheared layout (ShearLoC, Sec. 3.1, Algorithm 2): the coded order
+                         and the containers of 2 are those of 1; a decoder with order 2
+                         gathers each pixel's context from a window of the lane's
+                         sheared canvas, where every step is one column */
   int32_t patch_h;    /* patch rows; <= 0 or >= H: whole image */
   int32_t patch_w;    /* patch columns; <= 0 or >= W: whole image */
   int32_t interleave; /* rANS states per lane: 0 or 1 = one; 2 or 4 (wavefront order
@@ -148,6 +152,8 @@ typedef struct {
   int64_t ws_bytes;             /* workspace bytes the plan occupies */
   int64_t desc_offset;          /* byte offset of the descriptors in the workspace */
   int64_t counter_offset;       /* byte offset of the lane-queue counter */
+  int64_t ring_offset;          /* order 2: byte offset of the per-wave sheared context rings */
+  int64_t ring_rows;            /* order 2: rows of a ring (tallest lane + h, padded) */
 } nellox_decode_plan;
 
 nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nellox_image* out,

@@ -17,10 +17,11 @@ import torch
 
 from ._lib import NelloxDecodePlan, NelloxError, NelloxImage, NelloxOpts, check, load
 
-__all__ = ["Model", "NelloxError", "load", "RASTER", "WAVEFRONT"]
+__all__ = ["Model", "NelloxError", "load", "RASTER", "WAVEFRONT", "SHEARED"]
 
 RASTER = 0
 WAVEFRONT = 1
+SHEARED = 2  # the wavefront order, decoded in the sheared layout (ShearLoC)
 
 
 def _opts(order: int, patch, interleave: int = 1) -> NelloxOpts:

@@ -99,17 +99,25 @@ hipError_t stage_copy(nellox_model* m, void* dst, const void* src, size_t bytes,
 struct Plan {
   std::vector<ImgDesc> d;
   int64_t n_tiles = 0, n_lanes = 0, n_px = 0, slot_bytes = 0;
-  int K = 1;  // rANS streams per lane
+  int K = 1;       // rANS streams per lane
+  int order = 0;   // 0 raster, 1 wavefront, 2 wavefront decoded in the sheared layout
+  int ph_max = 0;  // tallest lane of the batch
+  int64_t ring_waves = 0, ring_rows = 0;  // sheared context rings (set by plan_ring)
 };
+
+// the coded order of a request: the sheared layout codes the wavefront order
+int coded_order(int order) { return order == 0 ? 0 : 1; }
 
 nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* o, Plan& P, bool need_px) {
   if (n < 0) return fail(NELLOX_E_ARG, "n < 0");
   if (n > 0 && !imgs) return fail(NELLOX_E_ARG, "imgs is null");
   if (!o) return fail(NELLOX_E_ARG, "opts is null");
-  if (o->order != 0 && o->order != 1) return fail(NELLOX_E_ARG, "order must be 0 (raster) or 1 (wavefront)");
+  if (o->order < 0 || o->order > 2)
+    return fail(NELLOX_E_ARG, "order must be 0 (raster), 1 (wavefront) or 2 (wavefront, sheared layout)");
+  P.order = o->order;
   P.K = o->interleave <= 1 ? 1 : o->interleave;
   if (!valid_interleave(P.K)) return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2 or 4");
-  if (P.K > 1 && o->order != 1) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
+  if (P.K > 1 && o->order == 0) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
   P.d.resize(n);
   for (int k = 0; k < n; ++k) {
     const nellox_image& im = imgs[k];
@@ -134,13 +142,14 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     P.n_lanes += nl;
     P.n_px += npx;
     P.n_tiles += (int64_t)im.H * D.ntx;
+    P.ph_max = std::max(P.ph_max, D.ph);
     P.slot_bytes += P.K * (6 * npx + 8 * nl);
   }
   return NELLOX_OK;
 }
 
 struct WsLayout {
-  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, total;
+  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, ring, total;
 };
 
 WsLayout ws_layout(const Plan& P, int n) {
@@ -148,6 +157,7 @@ WsLayout ws_layout(const Plan& P, int n) {
   int64_t o = 0;
   W.desc = o; o = align256(o + (int64_t)sizeof(ImgDesc) * std::max(n, 1));
   W.flags = o; o = align256(o + 64);
+  W.ring = o; o = align256(o + P.ring_waves * ring_wave_bytes(P.ring_rows));
   W.img_bytes = o; o = align256(o + 8LL * std::max(n, 1));
   W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
   W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
@@ -169,6 +179,24 @@ nellox_status hip_fail(hipError_t e, const char* what) {
 }
 
 int persistent_grid(const nellox_model* m) { return m->num_cu; }
+
+// the persistent decoder's launch shape: waves per workgroup = lanes per CU
+// (at most DECODE_WAVES), one workgroup per CU while lanes remain; the waves
+// of a CU share its LDS (weights, pivot tables, cross-lane traffic)
+void decode_shape(int64_t n_lanes, int cus, int& grid, int& waves) {
+  waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (n_lanes + cus - 1) / cus));
+  grid = (int)std::min<int64_t>(cus, (n_lanes + waves - 1) / waves);
+}
+
+// sheared layout: one context ring per wave of the launch, RING_COLS columns
+// of the tallest lane plus h zero rows on top
+void plan_ring(const nellox_model* m, Plan& P) {
+  if (P.order != 2 || P.n_lanes == 0) return;
+  int grid = 0, waves = 0;
+  decode_shape(P.n_lanes, m->num_cu, grid, waves);
+  P.ring_waves = (int64_t)grid * waves;
+  P.ring_rows = ring_rows_for(P.ph_max, m->h);
+}
 
 // upload the plan; fills the PassArgs common fields
 nellox_status upload_plan(nellox_model* m, const Plan& P, uint8_t* ws, const WsLayout& W, hipStream_t s) {
@@ -389,6 +417,7 @@ size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_ima
   if (!m) return 0;
   Plan P;
   if (make_plan(n, imgs, o, P, false) != NELLOX_OK) return 0;
+  plan_ring(m, P);
   return (size_t)ws_layout(P, n).total;
 }
 
@@ -414,7 +443,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   r.desc = (const ImgDesc*)(w8 + W.desc);
   r.n_img = n;
   r.n_lanes = P.n_lanes;
-  r.order = o->order;
+  r.order = coded_order(o->order);
   r.h = m->h;
   r.K = P.K;
   r.sym = (const uint32_t*)(w8 + W.sym);
@@ -426,7 +455,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   pk.desc = r.desc;
   pk.n_img = n;
   pk.n_lanes = P.n_lanes;
-  pk.order = o->order;
+  pk.order = coded_order(o->order);
   pk.h = m->h;
   pk.K = P.K;
   pk.model_hash = m->hash;
@@ -468,22 +497,22 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   Plan P;
   nellox_status st = make_plan(n, outs, o, P, true);
   if (st) return st;
+  plan_ring(m, P);
   if (n > 0 && !ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
   if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && (st = upload_plan(m, P, (uint8_t*)ws, W, s))) return st;
-  // spread the lanes over every CU: waves per workgroup = lanes per CU
-  // (at most DECODE_WAVES), one workgroup per CU while lanes remain; the
-  // waves of a CU share its LDS (weights, pivot tables, cross-lane traffic)
-  const int cus = persistent_grid(m);
-  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
+  int grid = 0, waves = 0;
+  decode_shape(P.n_lanes, persistent_grid(m), grid, waves);
   memset(plan, 0, sizeof(*plan));
   plan->n = n;
   plan->order = o->order;
   plan->interleave = P.K;
-  plan->waves = waves;
-  plan->grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
+  plan->waves = std::max(waves, 1);
+  plan->grid = grid;
+  plan->ring_offset = W.ring;
+  plan->ring_rows = P.ring_rows;
   plan->n_lanes = P.n_lanes;
   plan->model_hash = m->hash;
   plan->ws_bytes = W.total;
@@ -498,7 +527,9 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
                               const uint64_t* in_offsets, int32_t* status, uint32_t* dump, void* ws, void* stream) {
   if (check_model(m)) return NELLOX_E_ARG;
   if (!plan || plan->model_hash != m->hash || plan->n < 0 || plan->waves < 1 || plan->waves > DECODE_WAVES ||
-      !valid_interleave(plan->interleave))
+      !valid_interleave(plan->interleave) || plan->order < 0 || plan->order > 2 ||
+      (plan->order == 2 && plan->n_lanes > 0 &&
+       ((int64_t)plan->grid * plan->waves * ring_wave_bytes(plan->ring_rows) > plan->ws_bytes || plan->ring_rows < 4)))
     return fail(NELLOX_E_ARG, "plan does not belong to this model");
   const int n = plan->n;
   if (n == 0) return NELLOX_OK;
@@ -523,6 +554,8 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   a.status = status;
   a.counter = counter;
   a.sym_dump = dump;
+  a.ring = plan->order == 2 ? w8 + plan->ring_offset : nullptr;
+  a.ring_rows = (int)plan->ring_rows;
   e = launch_decode(m->h, m->Cp, a, plan->grid, plan->waves, s);
   if (e != hipSuccess) return hip_fail(e, "decoder launch");
   return NELLOX_OK;
@@ -573,6 +606,7 @@ nellox_status nellox_sample(const nellox_model* mc, int32_t n, const uint64_t* s
   Plan P;
   nellox_status st = make_plan(n, out, &so, P, true);
   if (st) return st;
+  plan_ring(m, P);
   if (n == 0) return NELLOX_OK;
   if (!ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
@@ -597,10 +631,10 @@ nellox_status nellox_sample(const nellox_model* mc, int32_t n, const uint64_t* s
   a.K = 4;
   a.model_hash = m->hash;
   a.counter = counter;
-  // the decoder's launch shape: lanes spread over every CU
-  const int cus = persistent_grid(m);
-  const int waves = (int)std::min<int64_t>(DECODE_WAVES, std::max<int64_t>(1, (P.n_lanes + cus - 1) / cus));
-  const int grid = (int)std::min<int64_t>(cus, (P.n_lanes + waves - 1) / waves);
+  a.ring = o->order == 2 ? w8 + W.ring : nullptr;
+  a.ring_rows = (int)P.ring_rows;
+  int grid = 0, waves = 0;
+  decode_shape(P.n_lanes, persistent_grid(m), grid, waves);
   e = launch_sample(m->h, m->Cp, a, grid, waves, s);
   if (e != hipSuccess) return hip_fail(e, "sampler launch");
   return NELLOX_OK;

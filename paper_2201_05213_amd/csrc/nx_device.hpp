@@ -194,6 +194,29 @@ NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uin
   }
 }
 
+// Context of pixel (i, t) of a lane from its sheared canvas window (Sec. 3.1,
+// Algorithm 2): tap (dy, dx) of the causal kernel is row i - h + dy, sheared
+// column t - h(h+2) + (h+1) dy + dx, always a column before t. The window
+// holds the int16 numerators 2x - 255 with 0 off the lane, so no bounds test
+// is needed and the value is the unsheared gather's, bit for bit. i must be
+// a row of the lane (callers clamp inactive rows).
+template <int H_>
+NXD void gather_ring(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const int16_t* ring, int rows, int t,
+                     int i, bool active) {
+  constexpr int o = H_ + 1, Q = H_ * (H_ + 2);
+  const __attribute__((address_space(1))) int16_t* g = (const __attribute__((address_space(1))) int16_t*)ring;
+  int raw[conv_chunks(H_)];
+#pragma unroll
+  for (int kc = 0; kc < conv_chunks(H_); ++kc) {
+    const uint32_t code = (tc.w[kc >> 2] >> (8 * (kc & 3))) & 0xffu;
+    const int dy = (int)(code & 3u), dx = (int)((code >> 2) & 7u), ch = (int)(code >> 5);
+    const int col = (t - Q + o * dy + dx) & (RING_COLS - 1);
+    raw[kc] = g[(uint32_t)((col * 3 + ch) * rows + i + dy)];
+  }
+#pragma unroll
+  for (int kc = 0; kc < conv_chunks(H_); ++kc) ctx[kc] = (float)(active ? raw[kc] : 0) * (1.0f / 255.0f);
+}
+
 // ------------------------------------------------------------------ network
 // The weight image is never written after it is staged in LDS, so the
 // compiler would hoist every weight read out of the persistent loops and try

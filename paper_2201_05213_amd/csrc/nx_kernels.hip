@@ -434,7 +434,9 @@ struct RowStream {
 // streams k) per iteration, their searches independent of each other.
 // SAMPLE: ancestral sampling instead of decoding (K = 4 structure, no
 // container): each symbol is the inverse quantised CDF at its Philox slot.
-template <int H_, int C_, bool TRACE, int K, bool SAMPLE>
+// SHEAR: the sheared layout (order 2): contexts from the wave's window of the
+// lane's sheared canvas instead of the output image.
+template <int H_, int C_, bool TRACE, int K, bool SAMPLE, bool SHEAR>
 __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int64_t L, int lane) {
   static_assert(!SAMPLE || K == 4, "sampling runs the four-row structure");
   const int p = lane & 15, g = lane >> 4;
@@ -460,7 +462,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   if (ok) {
     const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
     ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION &&
-         C[5] == (uint8_t)A.order && C[6] == (uint8_t)H_ && C[7] == (uint8_t)K && rd_u32(C + 8) == (uint32_t)D.H &&
+         C[5] == (uint8_t)(A.order == 0 ? 0 : 1) && C[6] == (uint8_t)H_ && C[7] == (uint8_t)K && rd_u32(C + 8) == (uint32_t)D.H &&
          rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
          (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
     ok = uniform(ok ? 1 : 0) != 0;
@@ -528,6 +530,19 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   uint8_t* img = D.px;
   const int o = H_ + 1;
   const bool raster = A.order == 0;
+  // sheared layout: this wave's window of the lane's sheared canvas, cleared
+  // (its h top rows stay 0: the padding above the lane)
+  constexpr bool shear = SHEAR;
+  const int rows = A.ring_rows;
+  int16_t* ring = nullptr;
+  if constexpr (shear) {
+    const int wave = uniform((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    ring = (int16_t*)(A.ring + (int64_t)wave * ring_wave_bytes(rows));
+    uint32_t* r32 = (uint32_t*)ring;
+    const int nw = (int)(ring_wave_bytes(rows) >> 2);
+    for (int k = lane; k < nw; k += 64) r32[k] = 0u;
+    __threadfence_block();
+  }
   const int64_t ngroups = raster ? (int64_t)Hl * Wl : (int64_t)Wl + (int64_t)o * (Hl - 1);
   uint32_t* dump = TRACE ? A.sym_dump + D.px_base * 3 : nullptr;
   TapCodes<H_> tc;
@@ -540,6 +555,19 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     } else {
       step_rows((int)gi, Hl, Wl, o, ilo, ihi);
     }
+    if constexpr (shear) {
+      // column gi of the window: rows of the lane outside this step hold no
+      // pixel of the step (0); the step's rows are written as they decode
+      int16_t* cb = ring + (int64_t)(gi & (RING_COLS - 1)) * 3 * rows + H_;
+      for (int r = lane; r < Hl; r += 64) {
+        if (r < ilo || r > ihi) {
+          cb[r] = 0;
+          cb[rows + r] = 0;
+          cb[2 * rows + r] = 0;
+        }
+      }
+      __threadfence_block();
+    }
     for (int ts = ilo; ts <= ihi; ts += 16) {
       const int na = min(16, ihi - ts + 1);
       const int i = ts + p;
@@ -547,7 +575,10 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       const int j = raster ? (int)(gi - (int64_t)ilo * Wl) : (int)gi - o * i;
       float ctx[conv_chunks(H_)];
       tc.refresh();
-      gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
+      if constexpr (shear)
+        gather_ring<H_>(ctx, tc, ring, rows, (int)gi, min(i, Hl - 1), active);
+      else
+        gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
       // sampling: the slots of pixel p (every lane group draws the same)
       uint32_t sl[3] = {0u, 0u, 0u};
       if constexpr (SAMPLE) sample_slots(D.seed, D.W, y0 + i, x0 + j, sl);
@@ -739,6 +770,12 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
         dst[0] = (uint8_t)xv[0];
         dst[1] = (uint8_t)xv[1];
         dst[2] = (uint8_t)xv[2];
+        if constexpr (shear) {
+          int16_t* cb = ring + (int64_t)(gi & (RING_COLS - 1)) * 3 * rows + H_ + i;
+          cb[0] = (int16_t)(2 * xv[0] - 255);
+          cb[rows] = (int16_t)(2 * xv[1] - 255);
+          cb[2 * rows] = (int16_t)(2 * xv[2] - 255);
+        }
       }
       // make this group's pixels visible to the wave's later gathers
       __threadfence_block();
@@ -755,7 +792,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   if (!clean) A.status[n] = ST_CORRUPT;
 }
 
-template <int H_, int C_, bool TRACE, int K, bool SAMPLE>
+template <int H_, int C_, bool TRACE, int K, bool SAMPLE, bool SHEAR>
 __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
@@ -769,7 +806,7 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
     if (lane == leader) L = atomicAdd(A.counter, 1);
     L = uniform(L);
     if ((int64_t)L >= A.n_lanes) break;
-    decode_lane<H_, C_, TRACE, K, SAMPLE>(A, w, piv, L, lane);
+    decode_lane<H_, C_, TRACE, K, SAMPLE, SHEAR>(A, w, piv, L, lane);
   }
 }
 
@@ -884,7 +921,10 @@ static hipError_t pass_t(const PassArgs& a, int grid, hipStream_t s) {
 template <int H_, int C_, bool TRACE, int K, bool SAMPLE = false>
 static hipError_t decode_tt(const DecArgs& a, int grid, int waves, hipStream_t s) {
   const size_t lds = (size_t)a.wfloats * 4 + (size_t)waves * WAVE_LDS_WORDS * 4;
-  hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K, SAMPLE>), dim3(grid), dim3(waves * 64), lds, s, a);
+  if (a.order == 2)
+    hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K, SAMPLE, true>), dim3(grid), dim3(waves * 64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_decode<H_, C_, TRACE, K, SAMPLE, false>), dim3(grid), dim3(waves * 64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -896,9 +936,12 @@ static hipError_t decode_setup_k() {
   int dev = 0, lim = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, K, false>, (size_t)lim);
-  if (e == hipSuccess) e = allow_lds(k_decode<H_, C_, true, K, false>, (size_t)lim);
-  if (K == 4 && e == hipSuccess) e = allow_lds(k_decode<H_, C_, false, 4, true>, (size_t)lim);
+  for (int sh = 0; sh < 2 && e == hipSuccess; ++sh) {
+    if (e == hipSuccess) e = allow_lds(sh ? k_decode<H_, C_, false, K, false, true> : k_decode<H_, C_, false, K, false, false>, (size_t)lim);
+    if (e == hipSuccess) e = allow_lds(sh ? k_decode<H_, C_, true, K, false, true> : k_decode<H_, C_, true, K, false, false>, (size_t)lim);
+    if (K == 4 && e == hipSuccess)
+      e = allow_lds(sh ? k_decode<H_, C_, false, 4, true, true> : k_decode<H_, C_, false, 4, true, false>, (size_t)lim);
+  }
   return e;
 }
 

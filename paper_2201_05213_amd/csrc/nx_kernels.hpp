@@ -71,6 +71,8 @@ struct DecArgs {
   int32_t* status;         // n_img
   int32_t* counter;        // work queue head
   uint32_t* sym_dump;      // nullable: (start | freq << 16) used per pixel/channel
+  uint8_t* ring;           // order 2: grid x waves context rings of ring_wave_bytes(ring_rows)
+  int ring_rows;
 };
 
 // Training objective and gradient (nx_train.hip). n images of H x W, all

@@ -64,6 +64,17 @@ struct ImgDesc {
 };
 static_assert(sizeof(ImgDesc) == 80, "descriptor layout");
 
+// Sheared layout (Sec. 3.1, Algorithm 2): a decoding wave keeps the last
+// RING_COLS columns of its lane's sheared canvas (column t = wavefront step
+// t), as int16 numerators 2x - 255 of the normalised values (0 = padding),
+// planes [column][channel][row]; rows = h zero rows on top, then the lane's
+// rows, padded to a multiple of 4. The sheared kernel reads h(h+2) columns
+// back, so RING_COLS > h(h+2) for every supported h.
+constexpr int RING_COLS = 16;
+static_assert(RING_COLS > 3 * (3 + 2), "ring too short for h = 3");
+NXHD inline int64_t ring_rows_for(int ph_max, int h) { return ((int64_t)ph_max + h + 3) & ~(int64_t)3; }
+NXHD inline int64_t ring_wave_bytes(int64_t rows) { return (int64_t)RING_COLS * 3 * rows * 2; }
+
 // Container header (little endian), followed by u32 end[n_lanes * K]
 // (cumulative payload bytes per stream, stream k of lane q at q K + k) and
 // the stream payloads (4 final-state bytes, then the renormalisation bytes in

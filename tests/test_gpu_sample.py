@@ -213,7 +213,7 @@ def test_edges_and_errors(nx):
     st = lambda *a: L.nellox_sample(m._h, *a)  # noqa: E731
     assert st(1, None, ctypes.byref(o), arr, ws.data_ptr(), ws.numel(), None) == 1  # null seeds
     assert st(1, seeds, None, arr, ws.data_ptr(), ws.numel(), None) == 1  # null opts
-    bad = _lib.NelloxOpts(2, 0, 0, 1)
+    bad = _lib.NelloxOpts(3, 0, 0, 1)
     assert st(1, seeds, ctypes.byref(bad), arr, ws.data_ptr(), ws.numel(), None) == 1  # bad order
     assert st(1, seeds, ctypes.byref(o), arr, ws.data_ptr(), 16, None) == 3  # workspace too small
     assert st(1, seeds, ctypes.byref(o), arr, None, ws.numel(), None) == 1  # null workspace
