@@ -432,13 +432,14 @@ struct RowStream {
 
 // K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
 // streams k) per iteration, their searches independent of each other.
-// SAMPLE: ancestral sampling instead of decoding (K = 4 structure, no
-// container): each symbol is the inverse quantised CDF at its Philox slot.
+// SAMPLE: ancestral sampling instead of decoding (no container): each
+// symbol is the inverse quantised CDF at its Philox slot, found by bisection
+// for all rows of a group at once (their slots do not depend on each other).
 // SHEAR: the sheared layout (order 2): contexts from the wave's window of the
 // lane's sheared canvas instead of the output image.
 template <int H_, int C_, bool TRACE, int K, bool SAMPLE, bool SHEAR>
 __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int64_t L, int lane) {
-  static_assert(!SAMPLE || K == 4, "sampling runs the four-row structure");
+  static_assert(!SAMPLE || K == 4, "sampling is instantiated once, as K = 4");
   const int p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
   const int n = find_img_uniform(A.desc, A.n_img, L);
@@ -592,7 +593,23 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       for (int c = 0; c < 3; ++c) {
         Chan Q;
         chan_params(M, c, xr, xg, Q);
-        if constexpr (K == 4) {
+        if constexpr (SAMPLE) {
+          // the v with cdf(v) <= slot < cdf(v + 1): eight halvings of
+          // [0, 256] with cdf(0) = 0 <= slot < cdf(256) = 2^16 kept; the
+          // evaluations are the encoder's (cdf_eval), so the draw is the
+          // inverse of the coder's own row
+          int lo = 0, hi = 256;
+#pragma unroll
+          for (int it = 0; it < 8; ++it) {
+            const int mid = (lo + hi) >> 1;
+            const bool le = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b)) <= sl[c];
+            lo = le ? mid : lo;
+            hi = le ? hi : mid;
+          }
+          if (c == 0) xv[0] = lo;
+          else if (c == 1) xv[1] = lo;
+          else xv[2] = lo;
+        } else if constexpr (K == 4) {
           // stage the channel's mixtures: lane (p, g) holds components g + 4 j
           float* mine = prm + p * PRM_STRIDE;
 #pragma unroll
@@ -631,7 +648,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             Mix10 P;
             load_mix10(P, prm, prc);
             const uint32_t pv = piv[prc * 16 + p];
-            const uint32_t slot = SAMPLE ? (uint32_t)__shfl((int)sl[c], prc) : RS.x & 0xffffu;
+            const uint32_t slot = RS.x & 0xffffu;
             const int b = row_count(__ballot(pv <= slot), g);
             const int k2 = 16 * b + p;
             const uint32_t c2 = cdf_quant(k2, cdf_eval10(max(k2, 1), P));
@@ -645,11 +662,9 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             const uint32_t lo = b == 0 ? 0u : lo_r;
             const uint32_t start = cnt == 0 ? lo : st_r;
             const uint32_t freq = (cnt < 15 ? nc_r : np_r) - start;
-            if constexpr (!SAMPLE) {
-              const uint32_t xn = freq * (RS.x >> 16) + slot - start;
-              RS.x = act ? xn : RS.x;
-              RS.renorm(act, p, g);
-            }
+            const uint32_t xn = freq * (RS.x >> 16) + slot - start;
+            RS.x = act ? xn : RS.x;
+            RS.renorm(act, p, g);
             // the symbol of pixel p (decoded by row p - q0) to all its lanes
             const int src = p - q0;
             const int sv = __shfl(sy, (src & 3) << 4);
