@@ -194,7 +194,7 @@ void plan_ring(const nellox_model* m, Plan& P) {
   if (P.order != 2 || P.n_lanes == 0) return;
   int grid = 0, waves = 0;
   decode_shape(P.n_lanes, m->num_cu, grid, waves);
-  P.ring_waves = (int64_t)grid * waves;
+  P.ring_waves = ring_windows(grid, waves);
   P.ring_rows = ring_rows_for(P.ph_max, m->h);
 }
 
@@ -529,7 +529,8 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   if (!plan || plan->model_hash != m->hash || plan->n < 0 || plan->waves < 1 || plan->waves > DECODE_WAVES ||
       !valid_interleave(plan->interleave) || plan->order < 0 || plan->order > 2 ||
       (plan->order == 2 && plan->n_lanes > 0 &&
-       ((int64_t)plan->grid * plan->waves * ring_wave_bytes(plan->ring_rows) > plan->ws_bytes || plan->ring_rows < 4)))
+       (ring_windows(plan->grid, plan->waves) * ring_wave_bytes(plan->ring_rows) > plan->ws_bytes ||
+        plan->ring_rows < 4)))
     return fail(NELLOX_E_ARG, "plan does not belong to this model");
   const int n = plan->n;
   if (n == 0) return NELLOX_OK;

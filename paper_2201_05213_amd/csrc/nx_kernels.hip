@@ -537,7 +537,12 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   const int rows = A.ring_rows;
   int16_t* ring = nullptr;
   if constexpr (shear) {
-    const int wave = uniform((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    // workgroups are dealt to the XCDs in turn: the windows of one XCD's
+    // waves are kept contiguous, so they spread over its L2 sets
+    const int nwv = (int)(blockDim.x >> 6);
+    const int xcd_blocks = (int)((gridDim.x + RING_XCDS - 1) / RING_XCDS);
+    const int slot = (int)(blockIdx.x % RING_XCDS) * xcd_blocks + (int)(blockIdx.x / RING_XCDS);
+    const int wave = uniform(slot * nwv + (int)(threadIdx.x >> 6));
     ring = (int16_t*)(A.ring + (int64_t)wave * ring_wave_bytes(rows));
     uint32_t* r32 = (uint32_t*)ring;
     const int nw = (int)(ring_wave_bytes(rows) >> 2);
@@ -557,15 +562,21 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       step_rows((int)gi, Hl, Wl, o, ilo, ihi);
     }
     if constexpr (shear) {
-      // column gi of the window: rows of the lane outside this step hold no
-      // pixel of the step (0); the step's rows are written as they decode
+      // column gi of the window: the step's rows [ilo, ihi] are written as
+      // they decode; of the other rows (no pixel at this column) only those
+      // a later read can reach are cleared: a pixel of step t' in (gi, gi +
+      // h(h+2)] reads rows i - h .. i with ilo(gi) <= ilo(t') <= i <=
+      // ihi(t') <= ihi(gi) + h + 1, so rows [ilo - h, ihi + h + 1] (at most
+      // 2h + 1 of them besides the step's); the rest are never read before
+      // the column is rewritten 16 steps later
       int16_t* cb = ring + (int64_t)(gi & (RING_COLS - 1)) * 3 * rows + H_;
-      for (int r = lane; r < Hl; r += 64) {
-        if (r < ilo || r > ihi) {
-          cb[r] = 0;
-          cb[rows + r] = 0;
-          cb[2 * rows + r] = 0;
-        }
+      const int r = (ilo <= ihi ? (lane < H_ ? ilo - H_ + lane : ihi + 1 + (lane - H_))
+                                : ilo - H_ + lane);
+      const int nz = ilo <= ihi ? 2 * H_ + 1 : 2 * H_ + 1 + (ihi + 1 - ilo);
+      if (lane < nz && r >= 0 && r < Hl) {
+        cb[r] = 0;
+        cb[rows + r] = 0;
+        cb[2 * rows + r] = 0;
       }
       __threadfence_block();
     }

@@ -74,6 +74,12 @@ constexpr int RING_COLS = 16;
 static_assert(RING_COLS > 3 * (3 + 2), "ring too short for h = 3");
 NXHD inline int64_t ring_rows_for(int ph_max, int h) { return ((int64_t)ph_max + h + 3) & ~(int64_t)3; }
 NXHD inline int64_t ring_wave_bytes(int64_t rows) { return (int64_t)RING_COLS * 3 * rows * 2; }
+// windows are grouped by XCD (workgroup b runs on XCD b mod RING_XCDS): a
+// launch of `grid` workgroups of `waves` waves needs this many windows
+constexpr int RING_XCDS = 8;
+NXHD inline int64_t ring_windows(int grid, int waves) {
+  return (int64_t)RING_XCDS * ((grid + RING_XCDS - 1) / RING_XCDS) * waves;
+}
 
 // Container header (little endian), followed by u32 end[n_lanes * K]
 // (cumulative payload bytes per stream, stream k of lane q at q K + k) and
