@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "nx_device.hpp"
 #include "nx_kernels.hpp"
 
@@ -292,17 +294,29 @@ __global__ void __launch_bounds__(TRAIN_WAVES * 64) k_train_bwd(TrainArgs A) {
 }
 
 // ------------------------------------------------------------------ weight gradients
-// One wave per (layer, chunk of pixels): D[row][col] = sum_px delta[px][row]
-// in[px][col] on v_mfma_f32_16x16x4f32 with K = 4 pixels per instruction
-// (A[i][k] = delta of pixel k, B[k][j] = input of pixel k), and the bias
-// gradient sum_px delta[px][row] from the same A values.
+// One workgroup per (layer, chunk of pixels): D[row][col] = sum_px
+// delta[px][row] in[px][col] on v_mfma_f32_16x16x4f32 with K = 4 pixels per
+// instruction (A[i][k] = delta of pixel k, B[k][j] = input of pixel k), and
+// the bias gradient sum_px delta[px][row] from the same A values. The chunk
+// is split over WGRAD_WAVES waves (consecutive pixel ranges), each loading
+// the next four pixels' operands while its MFMAs run on the current ones;
+// their sums are added in LDS in wave order, so the result does not depend
+// on timing.
+constexpr int WGRAD_WAVES = 4;
+constexpr int WGRAD_STEP = 8;  // pixels per prefetch (two MFMA K-steps of 4)
+
 template <int MO, int KI>
-__global__ void __launch_bounds__(64) k_wgrad(WgradArgs A) {
+__global__ void __launch_bounds__(WGRAD_WAVES * 64) k_wgrad(WgradArgs A) {
+  extern __shared__ float4 wg_smem[];
   const WgradLayer Lr = A.layer[blockIdx.y];
   const int64_t c = blockIdx.x;
-  const int64_t px_lo = c * A.chunk;
-  const int64_t px_hi = px_lo + A.chunk < A.npx ? px_lo + A.chunk : A.npx;
-  const int lane = threadIdx.x, i = lane & 15, k = lane >> 4;
+  const int64_t cl = c * A.chunk;
+  const int64_t ch = cl + A.chunk < A.npx ? cl + A.chunk : A.npx;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
+  // this wave's pixels: a quarter of the chunk, a multiple of WGRAD_STEP long
+  const int64_t part = ((A.chunk + WGRAD_WAVES - 1) / WGRAD_WAVES + WGRAD_STEP - 1) / WGRAD_STEP * WGRAD_STEP;
+  const int64_t px_lo = cl + wv * part < ch ? cl + wv * part : ch;
+  const int64_t px_hi = px_lo + part < ch ? px_lo + part : ch;
   f4 acc[MO][KI];
   float bacc[MO];
 #pragma unroll
@@ -311,32 +325,83 @@ __global__ void __launch_bounds__(64) k_wgrad(WgradArgs A) {
 #pragma unroll
     for (int kt = 0; kt < KI; ++kt) acc[mt][kt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   }
-  for (int64_t px0 = px_lo; px0 < px_hi; px0 += 4) {
-    const int64_t pk = px0 + k;
-    const bool ok = pk < px_hi;
-    const int64_t pc = ok ? pk : px_lo;
-    float a[MO], bv[KI];
+  // operands of pixels px0 + 4 s + k, s = 0, 1 (rows past the range read as 0)
+  float a[2][MO], bv[2][KI];
+  auto fetch = [&](int64_t px0, float (&fa)[2][MO], float (&fb)[2][KI]) {
 #pragma unroll
-    for (int mt = 0; mt < MO; ++mt) a[mt] = ok ? Lr.delta[pc * Lr.ld_delta + 16 * mt + i] : 0.0f;
+    for (int st = 0; st < 2; ++st) {
+      const int64_t pk = px0 + 4 * st + k;
+      const bool ok = pk < px_hi;
+      const int64_t pc = ok ? pk : cl;
 #pragma unroll
-    for (int kt = 0; kt < KI; ++kt) bv[kt] = ok ? Lr.in[pc * Lr.ld_in + 16 * kt + i] : 0.0f;
+      for (int mt = 0; mt < MO; ++mt) fa[st][mt] = ok ? Lr.delta[pc * Lr.ld_delta + 16 * mt + i] : 0.0f;
 #pragma unroll
-    for (int mt = 0; mt < MO; ++mt) {
-      bacc[mt] += a[mt];
+      for (int kt = 0; kt < KI; ++kt) fb[st][kt] = ok ? Lr.in[pc * Lr.ld_in + 16 * kt + i] : 0.0f;
+    }
+  };
+  if (px_lo < px_hi) fetch(px_lo, a, bv);
+  for (int64_t px0 = px_lo; px0 < px_hi; px0 += WGRAD_STEP) {
+    float na[2][MO], nb[2][KI];
+    const bool more = px0 + WGRAD_STEP < px_hi;
+    if (more) fetch(px0 + WGRAD_STEP, na, nb);
 #pragma unroll
-      for (int kt = 0; kt < KI; ++kt) acc[mt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], bv[kt], acc[mt][kt], 0, 0, 0);
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int mt = 0; mt < MO; ++mt) {
+        bacc[mt] += a[st][mt];
+#pragma unroll
+        for (int kt = 0; kt < KI; ++kt)
+          acc[mt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st][mt], bv[st][kt], acc[mt][kt], 0, 0, 0);
+      }
+    if (more) {
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+#pragma unroll
+        for (int mt = 0; mt < MO; ++mt) a[st][mt] = na[st][mt];
+#pragma unroll
+        for (int kt = 0; kt < KI; ++kt) bv[st][kt] = nb[st][kt];
+      }
     }
   }
+  // every wave parks its sums in LDS: value e of lane l at sm[(w PER + e) 64 + l]
+  constexpr int PER = MO * KI * 4 + MO;  // floats per lane
+  float* sm = (float*)wg_smem;
+  {
+    float* dst = sm + (int64_t)wv * PER * 64 + lane;
+#pragma unroll
+    for (int mt = 0; mt < MO; ++mt) {
+#pragma unroll
+      for (int kt = 0; kt < KI; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[((mt * KI + kt) * 4 + v) * 64] = acc[mt][kt][v];
+      dst[(MO * KI * 4 + mt) * 64] = bacc[mt];
+    }
+  }
+  __syncthreads();
+  // the workgroup adds the waves' values in wave order, one (value, lane) per
+  // thread at a time, and writes the partials
   float* out = A.partial + c * A.ngrad;
   const int N = 16 * KI;
+  for (int q = threadIdx.x; q < MO * KI * 4 * 64; q += WGRAD_WAVES * 64) {
+    const int e = q >> 6, l = q & 63;
+    float sum = sm[e * 64 + l];
 #pragma unroll
-  for (int mt = 0; mt < MO; ++mt) {
+    for (int w = 1; w < WGRAD_WAVES; ++w) sum = sum + sm[((int64_t)w * PER + e) * 64 + l];
+    const int v = e & 3, kt = (e >> 2) % KI, mt = (e >> 2) / KI;
+    const int li = l & 15, lk = l >> 4;
+    out[Lr.w_off + (int64_t)(16 * mt + 4 * lk + v) * N + 16 * kt + li] = sum;
+  }
+  // bias: per mt, lanes (i, k) hold partial sums over their pixels k; add the
+  // waves in order, then the four k groups as grp_sum does
+  if (wv == 0) {
 #pragma unroll
-    for (int kt = 0; kt < KI; ++kt)
+    for (int mt = 0; mt < MO; ++mt) {
+      float b = sm[(MO * KI * 4 + mt) * 64 + lane];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[Lr.w_off + (int64_t)(16 * mt + 4 * k + v) * N + 16 * kt + i] = acc[mt][kt][v];
-    const float bs = grp_sum(bacc[mt]);
-    if (k == 0) out[Lr.b_off + 16 * mt + i] = bs;
+      for (int w = 1; w < WGRAD_WAVES; ++w) b = b + sm[((int64_t)w * PER + MO * KI * 4 + mt) * 64 + lane];
+      const float bs = grp_sum(b);
+      if (k == 0) out[Lr.b_off + 16 * mt + i] = bs;
+    }
   }
 }
 
@@ -367,9 +432,21 @@ __global__ void k_grad_reduce(GradReduceArgs A) {
     } else {
       src = A.bias_head + head_row_of((int)(idx - P.head_b));
     }
+    // chunk partials added in chunk order; loaded 16 at a time so that many
+    // loads are in flight
     double s = 0.0;
-    if (src >= 0)
-      for (int64_t c = 0; c < A.nchunks; ++c) s += (double)A.partial[c * A.ngrad + src];
+    if (src >= 0) {
+      const float* col = A.partial + src;
+      int64_t c = 0;
+      for (; c + 16 <= A.nchunks; c += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = col[(c + u) * A.ngrad];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += (double)v[u];
+      }
+      for (; c < A.nchunks; ++c) s += (double)col[c * A.ngrad];
+    }
     A.grad[idx] = (float)s;
   }
 }
@@ -428,7 +505,9 @@ static hipError_t train_bwd_t(const TrainArgs& a, int grid, hipStream_t s) {
 
 hipError_t launch_swizzle(const float* params, int h, int C, int Cp, int nb, float* wimg, int64_t nw, float* wimgT,
                           int64_t nwT, hipStream_t s) {
-  hipLaunchKernelGGL(k_swizzle, dim3(64), dim3(256), 0, s, params, h, C, Cp, nb, wimg, nw, wimgT, nwT);
+  // one element per thread: the index maps are a few divisions each
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nw + nwT + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_swizzle, dim3((unsigned)blocks), dim3(256), 0, s, params, h, C, Cp, nb, wimg, nw, wimgT, nwT);
   return hipGetLastError();
 }
 
@@ -442,7 +521,11 @@ hipError_t launch_train_bwd(int h, int Cp, const TrainArgs& a, int grid, hipStre
 
 template <int MO, int KI>
 static hipError_t wgrad_t(const WgradArgs& a, int nlayers, hipStream_t s) {
-  hipLaunchKernelGGL((k_wgrad<MO, KI>), dim3((unsigned)a.nchunks, (unsigned)nlayers), dim3(64), 0, s, a);
+  const size_t lds = (size_t)WGRAD_WAVES * (MO * KI * 4 + MO) * 64 * sizeof(float);
+  hipError_t e = allow_lds_t(k_wgrad<MO, KI>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_wgrad<MO, KI>), dim3((unsigned)a.nchunks, (unsigned)nlayers), dim3(WGRAD_WAVES * 64), lds, s,
+                     a);
   return hipGetLastError();
 }
 
