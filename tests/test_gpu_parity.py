@@ -404,3 +404,35 @@ def test_corrupt_streams_detected(models, nx, K):
     bad[32 + 4 * (nl * K - 1)] ^= 0x7F
     _, st = m.decode(bad, offs, [(40, 40)], order=1, patch=(20, 20), interleave=K, sync=False)
     assert int(st[0]) == 4
+
+
+@pytest.mark.parametrize("shape,patch,orders", [
+    ((1, 65535), None, (0, 1, 2)),          # one row of the maximum width, whole-image lane
+    ((65535, 1), (4096, 1), (1, 2)),        # the maximum height, 16 lanes of 4096 rows
+    ((65535, 1), None, (1, 2)),             # the maximum height as one lane: 262,137 wavefront steps
+])
+def test_maximum_sides(models, nx, shape, patch, orders):
+    """Sides of 65535 (the largest H, W the ABI takes) round trip exactly in
+    every order; 65536 is refused; sampling at the maximum width inverts the
+    GPU's own CDF."""
+    m, _, _ = models["C"]
+    H, W = shape
+    img = synth.smooth_field_image(2.0, 3, 2, H, W, 6000 + H % 7)
+    t = cuda(img)
+    for order in orders:
+        say(f"[gpu] maximum side {shape} patch {patch} order {order}")
+        data, offs = m.encode([t], order=order, patch=patch)
+        (out,), _ = m.decode(data, offs, [shape], order=order, patch=patch)
+        assert torch.equal(out, t)
+    big = torch.zeros((1, 65536, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(nx.NelloxError):
+        m.encode([big])
+    if H == 1 and patch is None:
+        from sample_ref import numpy_slots
+
+        (smp,) = m.sample([shape], [99])
+        sym, _ = m.debug_symbols([smp])
+        s = sym.cpu().numpy().view(np.uint32).reshape(H, W, 3)
+        start, freq = (s & 0xFFFF).astype(np.int64), (s >> 16).astype(np.int64)
+        slot = numpy_slots(99, H, W)
+        assert np.all(start <= slot) and np.all(slot < start + freq)
