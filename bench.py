@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--cpu-lanes", type=int, default=48, help="64x64 lanes the oracle decodes")
     ap.add_argument("--train-steps", type=int, default=50,
                     help="timed training steps (model B, 64 random 32x32 crops, Adam); 0 skips the leg")
+    ap.add_argument("--no-trained", action="store_true",
+                    help="skip the trained-model leg (model B after the 2000-step training recipe: decode time "
+                         "and the bits gap at about 3 bits/dim)")
     ap.add_argument("--profile", action="store_true",
                     help="time only the batch decode, then run a known-size copy for counter calibration "
                          "(for profiler runs; prints no JSON line)")
@@ -373,6 +376,67 @@ def main():
                      "sample": "model B, 64 random 32x32 crops per step, forward + backward + Adam"}
         log(f"[bench] training step {tstep * 1e3:.3f} ms ({tflops / 1e12:.1f} TFLOP/s fwd+bwd)")
 
+    # the same workload coded by a trained model B (the 2000-step training
+    # recipe, ~3 bits/dim): decode time and, on the oracle's sampled lanes,
+    # the gap with the configured streams and with one stream
+    trained_rec = None
+    if not args.no_trained:
+        from paper_2201_05213_amd import blob as nxblob, train as nxtrain
+
+        tdims, tparams = nxblob.params_from_blob(blob)
+        tpool = torch.from_numpy(synth.training_pool(n=512)).to(dev)
+        t0 = time.time()
+        tp = nxtrain.fit(torch.from_numpy(tparams).to(dev), tdims, tpool, 2000,
+                         np.random.Generator(np.random.PCG64(5_999_999)))
+        torch.cuda.synchronize()
+        fit_s = time.time() - t0
+        mt = nx.Model(nxblob.blob_from_params(tdims, tp.cpu().numpy()))
+        td, to = mt.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave)
+        plan3, ws3 = mt.decode_prepare(outs, order=dec_order, patch=patch, interleave=args.interleave)
+        mt.decode_run(plan3, td, to, status, ws3)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(nrep):
+            mt.decode_run(plan3, td, to, status, ws3)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts)), "round trip failed (trained model)"
+        assert int(status.abs().sum()) == 0
+        t_step = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
+        tc = td.cpu().numpy()
+        toh = to.cpu().numpy()
+        tbits = 0
+        for k in range(len(imgs)):
+            c = tc[toh[k]:toh[k + 1]]
+            nl = int.from_bytes(bytes(c[28:32]), "little")
+            tbits += 8 * (len(c) - 32 - 4 * nl * int(c[7]))
+        trained_rec = {"train_s": fit_s, "bits_per_dim": tbits / (3 * npx), "decode_ms": t_step * 1e3,
+                       "px_per_s": npx / t_step}
+        log(f"[bench] trained model B ({fit_s:.1f}s to train): {tbits / (3 * npx):.3f} bits/dim, decode "
+            f"{t_step * 1e3:.2f} ms ({npx / t_step / 1e6:.0f} Mpx/s)")
+        del ws3
+        if not args.no_cpu:
+            import oracle
+
+            tom = oracle.Model.from_blob(nxblob.blob_from_params(tdims, tp.cpu().numpy()))
+            lanes_x = 1024 // args.patch
+            sample = [0, lanes_x + 3, (1024 // args.patch) ** 2 - 1]
+            crops = [np.ascontiguousarray(imgs[0][(q // lanes_x) * args.patch:(q // lanes_x + 1) * args.patch,
+                                                  (q % lanes_x) * args.patch:(q % lanes_x + 1) * args.patch])
+                     for q in sample]
+            ideal = sum(tom.stats(c)["qbits"] for c in crops)
+            for K in sorted({args.interleave, 1}):
+                dK, oK = mt.encode([ts[0]], order=nx.WAVEFRONT, patch=patch, interleave=K)
+                c0 = dK.cpu().numpy()
+                nl0 = int.from_bytes(bytes(c0[28:32]), "little")
+                ends = np.frombuffer(bytes(c0[32:32 + 4 * nl0 * K]), dtype="<u4").astype(np.int64)
+                lb = np.diff(np.concatenate([[0], ends])).reshape(nl0, K).sum(axis=1) * 8
+                got = float(sum(lb[q] for q in sample))
+                trained_rec[f"gap_vs_oracle_ideal_k{K}"] = (got - ideal) / ideal
+                log(f"[bench] trained model B, {K} stream(s): gap on {len(sample)} lanes "
+                    f"{100 * (got - ideal) / ideal:.4f}% ({(got - ideal) / len(sample):.1f} bits per lane)")
+            trained_rec["gap_sample"] = f"lanes {sample} of image 0, {args.patch}x{args.patch}"
+
     out = {
         "metric": "decoded pixels/sec on 1 GPU, wavefront+patch vs raster; bits/dim gap vs FP64 oracle",
         "value": value,
@@ -414,6 +478,7 @@ def main():
                      "traffic": decode_traffic_bytes(args.layout), "traffic_unit": "HBM bytes per launch"},
         "cpu_baseline": cpu,
         "training": train_rec,
+        "trained_model": trained_rec,
     }
     print(json.dumps(out))
 
