@@ -6,6 +6,7 @@ per image for 0/1/3 residual blocks at 32x32, and for image sides 32 to
 random-init local models with h = 3.
 
     python -m paper_2201_05213_amd.sweep > table.md
+    python -m paper_2201_05213_amd.sweep --patches   # large batch: patch shape x streams
 """
 from __future__ import annotations
 
@@ -103,9 +104,39 @@ def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
         pr(f"| {side} | {tr * 1e3:.2f} ms{rnote} | {tw * 1e3:.2f} ms | {tr / tw:.1f}x | {sp} |")
 
 
+def run_patches(out=sys.stdout, shapes=((32, 64), (64, 64), (128, 64), (64, 128), (128, 128), (96, 96)),
+                streams=(4, 2, 1), reps=3):
+    """Decode time of the large batch (4 x 1024^2 + 2 x 2048x1536, model B,
+    wavefront order) by patch shape and rANS streams per lane."""
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pr = lambda s: print(s, file=out, flush=True)  # noqa: E731
+    ts = [torch.from_numpy(i).to(dev) for i in synth.workload_images("large6")]
+    m = nx.Model(synth.model_blob("B")[0])
+    pr("| patch (rows x cols) | lanes | waves/CU | " + " | ".join(f"{k} stream(s)" for k in streams) + " |")
+    pr("|---|---|---|" + "---|" * len(streams))
+    for patch in shapes:
+        cells, lanes, waves = [], 0, 0
+        for K in streams:
+            data, offs = m.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=K)
+            outs = [torch.empty_like(t) for t in ts]
+            plan, ws = m.decode_prepare(outs, order=nx.WAVEFRONT, patch=patch, interleave=K)
+            lanes, waves = plan.n_lanes, plan.waves
+            cells.append(f"{time_decode(m, ts, nx.WAVEFRONT, patch=patch, interleave=K, reps=reps) * 1e3:.2f} ms")
+            del ws
+        pr(f"| {patch[0]} x {patch[1]} | {lanes} | {waves} | " + " | ".join(cells) + " |")
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--channels", type=int, default=32)
     ap.add_argument("--raster-rows", type=int, default=8)
+    ap.add_argument("--patches", action="store_true",
+                    help="instead: decode time of the large batch by patch shape and streams per lane")
     a = ap.parse_args()
-    run(a.channels, a.raster_rows)
+    if a.patches:
+        run_patches()
+    else:
+        run(a.channels, a.raster_rows)
