@@ -72,12 +72,12 @@ static_assert(sizeof(ImgDesc) == 80, "descriptor layout");
 // back, so RING_COLS > h(h+2) for every supported h.
 constexpr int RING_COLS = 16;
 static_assert(RING_COLS > 3 * (3 + 2), "ring too short for h = 3");
-NXHD inline int64_t ring_rows_for(int ph_max, int h) { return ((int64_t)ph_max + h + 3) & ~(int64_t)3; }
-NXHD inline int64_t ring_wave_bytes(int64_t rows) { return (int64_t)RING_COLS * 3 * rows * 2; }
+NXHD int64_t ring_rows_for(int ph_max, int h) { return ((int64_t)ph_max + h + 3) & ~(int64_t)3; }
+NXHD int64_t ring_wave_bytes(int64_t rows) { return (int64_t)RING_COLS * 3 * rows * 2; }
 // windows are grouped by XCD (workgroup b runs on XCD b mod RING_XCDS): a
 // launch of `grid` workgroups of `waves` waves needs this many windows
 constexpr int RING_XCDS = 8;
-NXHD inline int64_t ring_windows(int grid, int waves) {
+NXHD int64_t ring_windows(int grid, int waves) {
   return (int64_t)RING_XCDS * ((grid + RING_XCDS - 1) / RING_XCDS) * waves;
 }
 
