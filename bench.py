@@ -90,7 +90,7 @@ def main():
                          "(for profiler runs; prints no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; the library has no multi-GPU path"}))
         sys.exit(2)
 
     import numpy as np

@@ -61,7 +61,7 @@ typedef enum {
   NELLOX_E_CORRUPT = 4,        /* (device status) container damaged */
   NELLOX_E_MODEL_MISMATCH = 5, /* (device status) container made by another model */
   NELLOX_E_HIP = 6,            /* a HIP runtime call failed */
-  NELLOX_E_UNSUPPORTED = 7     /* model dimensions this build has no kernel for */
+  NELLOX_E_UNSUPPORTED = 7     /* model dimensions the library has no kernel for */
 } nellox_status;
 
 typedef struct {
