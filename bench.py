@@ -228,6 +228,32 @@ def main():
         f"headline is {alt_step / step_s:.3f}x faster")
     del ws2
 
+    # variants of the large-image workload: the h = 2, 32-channel model C, and
+    # 32x32 patches with model B (prepared runs, round trips checked)
+    variants = {}
+    for vname, mname, vpatch in (("model_C_p64", "C", patch), ("model_B_p32", "B", (32, 32))):
+        mv = m if mname == "B" else nx.Model(synth.model_blob(mname)[0])
+        vd, vo = mv.encode(ts, order=nx.WAVEFRONT, patch=vpatch, interleave=args.interleave)
+        vplan, vws = mv.decode_prepare(outs, order=nx.WAVEFRONT, patch=vpatch, interleave=args.interleave)
+        mv.decode_run(vplan, vd, vo, status, vws)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(nrep):
+            mv.decode_run(vplan, vd, vo, status, vws)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts)), f"round trip failed ({vname})"
+        assert int(status.abs().sum()) == 0
+        vstep = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
+        vh, vC, vnb = (synth.MODEL_DIMS[mname][k] for k in ("h", "C", "n_blocks"))
+        vflops = 2 * macs_per_px(vh, vC, vnb) * npx / vstep
+        variants[vname] = {"ms": vstep * 1e3, "px_per_s": npx / vstep, "tflops": vflops / 1e12,
+                           "frac_fp32_peak": vflops / PEAK_FP32, "patch": list(vpatch),
+                           "model": f"h={vh}, C={vC}, {vnb} block(s)"}
+        log(f"[bench] {vname}: decode {vstep * 1e3:.2f} ms ({npx / vstep / 1e6:.0f} Mpx/s, "
+            f"{100 * vflops / PEAK_FP32:.1f}% of FP32 peak)")
+        del vws
+
     # ancestral sampling of the same batch shape with the decoder's schedule
     # (each symbol the inverse quantised CDF at a Philox slot; no coder)
     smp_out = [torch.empty_like(t) for t in ts]
@@ -468,6 +494,7 @@ def main():
         "encode_s_untimed": enc_s,
         "encode": enc_rec,
         "sampling": smp_rec,
+        "variants": variants,
         "other_layout_decode": alt_rec,
         "bits_per_dim": bpd,
         "gap_vs_oracle_ideal": gap,
