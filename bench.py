@@ -254,6 +254,46 @@ def main():
             f"{100 * vflops / PEAK_FP32:.1f}% of FP32 peak)")
         del vws
 
+    # the other batch workloads with model B: 512 images of 32x32 (one lane
+    # and one stream per image) and the uneven 64-image batch with the patch
+    # shape and streams chosen by the autotuner (within 0.1% of the best bits)
+    from paper_2201_05213_amd import tune
+
+    def time_workload(wimgs, wpatch, K):
+        wd, wo = m.encode(wimgs, order=nx.WAVEFRONT, patch=wpatch, interleave=K)
+        wout = [torch.empty_like(t) for t in wimgs]
+        wst = torch.empty(len(wimgs), dtype=torch.int32, device=dev)
+        wplan, wws = m.decode_prepare(wout, order=nx.WAVEFRONT, patch=wpatch, interleave=K)
+        m.decode_run(wplan, wd, wo, wst, wws)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(nrep):
+            m.decode_run(wplan, wd, wo, wst, wws)
+        ev[1].record(stream)
+        for _ in range(nrep):
+            m.encode(wimgs, order=nx.WAVEFRONT, patch=wpatch, interleave=K, sync=False)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(wout, wimgs)) and int(wst.abs().sum()) == 0
+        wpx = sum(int(t.shape[0]) * int(t.shape[1]) for t in wimgs)
+        dms = ev[0].elapsed_time(ev[1]) / nrep
+        ems = ev[1].elapsed_time(ev[2]) / nrep
+        return {"images": len(wimgs), "pixels": wpx, "patch": None if wpatch is None else list(wpatch),
+                "interleave": K, "decode_ms": dms, "decode_px_per_s": wpx / dms * 1e3, "encode_ms": ems,
+                "encode_px_per_s": wpx / ems * 1e3}
+
+    workloads = {}
+    b512 = [torch.from_numpy(i).to(dev) for i in synth.workload_images("batch512x32")]
+    workloads["batch512x32"] = time_workload(b512, None, 1)
+    un64 = [torch.from_numpy(i).to(dev) for i in synth.workload_images("uneven64")]
+    choice, _ = tune.autotune(m, un64)
+    workloads["uneven64"] = time_workload(un64, choice["patch"], choice["interleave"])
+    workloads["uneven64"]["autotuned"] = True
+    del b512, un64
+    for wn, w in workloads.items():
+        log(f"[bench] {wn}: decode {w['decode_ms']:.2f} ms ({w['decode_px_per_s'] / 1e6:.0f} Mpx/s), encode "
+            f"{w['encode_ms']:.2f} ms, patch {w['patch']}, {w['interleave']} stream(s)")
+
     # ancestral sampling of the same batch shape with the decoder's schedule
     # (each symbol the inverse quantised CDF at a Philox slot; no coder)
     smp_out = [torch.empty_like(t) for t in ts]
@@ -495,6 +535,7 @@ def main():
         "encode": enc_rec,
         "sampling": smp_rec,
         "variants": variants,
+        "other_workloads": workloads,
         "other_layout_decode": alt_rec,
         "bits_per_dim": bpd,
         "gap_vs_oracle_ideal": gap,
