@@ -633,32 +633,19 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // pivots of pixel p: lane group g evaluates j = 4 g .. 4 g + 3
-          // (cdf at k = 16 (j + 1); j = 15 stands for k = 256)
-          {
-            Mix10 P;
-            load_mix10(P, prm, p);
-            uint32_t pvv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int j = 4 * g + i;
-              const int kk = min(16 * (j + 1), 255);
-              const uint32_t v = cdf_quant(kk, cdf_eval10(kk, P));
-              pvv[i] = j < 15 ? v : CDF_TOTAL;
-            }
-            *(uint4*)(piv + p * 16 + 4 * g) = make_uint4(pvv[0], pvv[1], pvv[2], pvv[3]);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // pops: row g takes row ts + q0 + g of the group (stream g)
+          // pops: row g takes row ts + q0 + g of the group (stream g); lane p
+          // of the row first evaluates pivot p of that pixel, the cdf at
+          // k = 16 (p + 1) (p = 15 stands for k = 256): it does not depend on
+          // the coder state, and only the rows that are popped are evaluated
           for (int q0 = 0; q0 < na; q0 += 4) {
             const int pr = q0 + g;
             const bool act = pr < na;
             const int prc = min(pr, 15);
             Mix10 P;
             load_mix10(P, prm, prc);
-            const uint32_t pv = piv[prc * 16 + p];
+            const int kp = min(16 * (p + 1), 255);
+            const uint32_t pq = cdf_quant(kp, cdf_eval10(kp, P));
+            const uint32_t pv = p < 15 ? pq : CDF_TOTAL;
             const uint32_t slot = RS.x & 0xffffu;
             const int b = row_count(__ballot(pv <= slot), g);
             const int k2 = 16 * b + p;
