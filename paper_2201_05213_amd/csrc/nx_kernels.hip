@@ -653,12 +653,14 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             const int cnt = row_count(__ballot(c2 <= slot) & 0xfffefffefffefffeull, g);
             const int sy = 16 * b + cnt;
             const int rb = g << 4;
-            const uint32_t lo_r = (uint32_t)__shfl((int)pv, rb | ((b + 15) & 15));
+            // start = cdf(16 b + cnt): lane cnt's value, lane 0's being the
+            // bucket's lower edge cdf(16 b) (the same evaluation as pivot
+            // b - 1), except cdf(0) = 0; end = cdf(16 b + cnt + 1): lane
+            // cnt + 1's value, or the bucket's upper edge, pivot b
             const uint32_t st_r = (uint32_t)__shfl((int)c2, rb | cnt);
             const uint32_t nc_r = (uint32_t)__shfl((int)c2, rb | ((cnt + 1) & 15));
             const uint32_t np_r = (uint32_t)__shfl((int)pv, rb | b);
-            const uint32_t lo = b == 0 ? 0u : lo_r;
-            const uint32_t start = cnt == 0 ? lo : st_r;
+            const uint32_t start = (b == 0 && cnt == 0) ? 0u : st_r;
             const uint32_t freq = (cnt < 15 ? nc_r : np_r) - start;
             const uint32_t xn = freq * (RS.x >> 16) + slot - start;
             RS.x = act ? xn : RS.x;
