@@ -407,12 +407,6 @@ struct RowStream {
     }
     word = v;
   }
-  // byte at q of this row's window (every lane of the wave takes part)
-  NXD uint32_t byte_at(uint32_t q, int g) const {
-    const uint32_t off = q - base;
-    const uint32_t v = (uint32_t)__shfl((int)word, (g << 4) | (int)((off >> 2) & 15u));
-    return (v >> (8 * (off & 3u))) & 255u;
-  }
   // renormalisation after a pop of this row (as ByteStage::renorm): the window
   // is moved first where it would not hold pos + 1
   NXD void renorm(bool act, int p, int g) {
@@ -420,7 +414,14 @@ struct RowStream {
     if (__ballot(need) != 0ull) {
       if (need) fill(pos & ~3u, p);
     }
-    const uint32_t b0 = byte_at(pos, g), b1 = byte_at(pos + 1u, g);
+    // bytes pos and pos + 1 (off <= 62 here): the two window words from
+    // off / 4 on, then the byte pair at off % 4 of their concatenation
+    const uint32_t off = pos - base;
+    const uint32_t wi = off >> 2;
+    const uint32_t w0 = (uint32_t)__shfl((int)word, (g << 4) | (int)(wi & 15u));
+    const uint32_t w1 = (uint32_t)__shfl((int)word, (g << 4) | (int)((wi + 1u) & 15u));
+    const uint32_t two = __builtin_amdgcn_alignbyte(w1, w0, off & 3u);
+    const uint32_t b0 = two & 255u, b1 = (two >> 8) & 255u;
     const bool r0 = act && x < RANS_L && pos < len;
     x = r0 ? ((x << 8) | b0) : x;
     pos += r0 ? 1u : 0u;
