@@ -4,9 +4,11 @@ same GPU's raster decode, bits/dim gap vs the FP64 oracle.
 Workload (synthetic, seeded): 4 images of 1024x1024 and 2 of 2048x1536 uint8
 RGB (smooth random fields, sigma 4 px, 20 step edges, +-3 integer noise),
 coded with the h=3, 64-channel, 2-block local model (random-init weights) in
-the wavefront order with independent 64x64 patches, each patch one lane of
-4 interleaved rANS streams. One timed step = one decode of the whole batch
-from containers already resident in HBM.
+the wavefront order with independent 96x64 patches (96 rows, 64 columns),
+each patch one lane of 4 interleaved rANS streams. One timed step = one decode
+of the whole batch from containers already resident in HBM, by default in the
+sheared layout (ShearLoC, Sec. 3.1 and Algorithm 2); the unsheared wavefront
+decoder (Algorithm 1) is timed on the same containers as a second leg.
 
 Prints one JSON line (see the keys below); --gpus N > 1 is refused: this
 path runs on one GPU.
@@ -28,13 +30,13 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 
 # HBM bytes per decoder launch on this workload from two counter passes
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a
-# 256 MiB device copy, per decoder layout; valid only for the kernel sources
-# they were taken on
+# 256 MiB device copy, per decoder layout; valid only for the kernel sources,
+# patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "unsheared": {"src_sha": "d333ac4c7249ba81", "fetch_kib": 38949.6, "write_kib": 33335.8,
-                  "fetch_scale": 1.9998, "write_scale": 1.0},
-    "sheared": {"src_sha": "d333ac4c7249ba81", "fetch_kib": 27541.6, "write_kib": 445389.9,
-                "fetch_scale": 1.99981, "write_scale": 1.0},
+    "sheared": {"src_sha": "d333ac4c7249ba81", "patch": (96, 64), "interleave": 4,
+                "fetch_kib": 28022.9, "write_kib": 392889.8, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "unsheared": {"src_sha": "d333ac4c7249ba81", "patch": (96, 64), "interleave": 4,
+                  "fetch_kib": 38049.9, "write_kib": 31565.8, "fetch_scale": 1.9998, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
@@ -49,9 +51,9 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def decode_traffic_bytes(layout: str):
+def decode_traffic_bytes(layout: str, patch, interleave: int):
     t = DECODE_TRAFFIC[layout]
-    if kernel_sources_sha() != t["src_sha"]:
+    if kernel_sources_sha() != t["src_sha"] or tuple(patch) != t["patch"] or interleave != t["interleave"]:
         return None
     return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 
@@ -71,15 +73,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--patch", type=int, default=64)
+    ap.add_argument("--patch", default="96x64",
+                    help="patch shape ROWSxCOLS (or one number for square patches)")
     ap.add_argument("--interleave", type=int, default=4, help="rANS streams per lane (1, 2 or 4)")
-    ap.add_argument("--layout", choices=("sheared", "unsheared"), default="unsheared",
+    ap.add_argument("--layout", choices=("sheared", "unsheared"), default="sheared",
                     help="decoder layout of the headline decode: sheared (ShearLoC, Algorithm 2) or the "
                          "unsheared wavefront decoder (Algorithm 1); the other is timed as a second leg")
     ap.add_argument("--raster-rows", type=int, default=32,
                     help="rows of the 1024-wide strip the raster baseline decodes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-lanes", type=int, default=48, help="64x64 lanes the oracle decodes")
+    ap.add_argument("--cpu-lanes", type=int, default=32, help="lanes of image 0 the oracle decodes")
     ap.add_argument("--train-steps", type=int, default=50,
                     help="timed training steps (model B, 64 random 32x32 crops, Adam); 0 skips the leg")
     ap.add_argument("--no-trained", action="store_true",
@@ -109,7 +112,14 @@ def main():
     ts = [torch.from_numpy(i).to(dev) for i in imgs]
     shapes = [i.shape[:2] for i in imgs]
     npx = sum(h * w for h, w in shapes)
-    patch = (args.patch, args.patch)
+    ph, pw = (int(v) for v in (args.patch.split("x") if "x" in args.patch else (args.patch, args.patch)))
+    patch = (ph, pw)
+    pname = f"{ph}x{pw}"
+    lanes_x = -(-1024 // pw)  # lanes across a 1024-wide image
+
+    def lane_crop(img, q):
+        ly, lx = divmod(q, lanes_x)
+        return np.ascontiguousarray(img[ly * ph:(ly + 1) * ph, lx * pw:(lx + 1) * pw])
 
     # encode once (untimed), containers stay in HBM
     torch.cuda.synchronize()
@@ -222,19 +232,25 @@ def main():
     alt_step = ev[0].elapsed_time(ev[1]) / 1e3 / nrep
     alt_name = "unsheared" if args.layout == "sheared" else "sheared"
     alt_rec = {"layout": alt_name, "px_per_s": npx / alt_step, "ms": alt_step * 1e3,
-               "headline_speedup": alt_step / step_s, "traffic": decode_traffic_bytes(alt_name),
+               "headline_speedup": alt_step / step_s,
+               "traffic": decode_traffic_bytes(alt_name, patch, args.interleave),
                "sample": f"the timed containers decoded in the {alt_name} layout (prepared run), round trip checked"}
     log(f"[bench] {alt_name} decode {alt_step * 1e3:.2f} ms ({npx / alt_step / 1e6:.0f} Mpx/s); the {args.layout} "
         f"headline is {alt_step / step_s:.3f}x faster")
     del ws2
 
-    # variants of the large-image workload: the h = 2, 32-channel model C, and
-    # 32x32 patches with model B (prepared runs, round trips checked)
+    # variants of the large-image workload, in the headline's decoder layout:
+    # model B on 64x64 and 32x32 patches, and the h = 2, 32-channel model C on
+    # the headline's patches and on 64x64 (prepared runs, round trips checked)
     variants = {}
-    for vname, mname, vpatch in (("model_C_p64", "C", patch), ("model_B_p32", "B", (32, 32))):
-        mv = m if mname == "B" else nx.Model(synth.model_blob(mname)[0])
+    mc = nx.Model(synth.model_blob("C")[0])
+    for mname, vpatch in dict.fromkeys((("B", (64, 64)), ("B", (32, 32)), ("C", patch), ("C", (64, 64)))):
+        if mname == "B" and vpatch == patch:
+            continue  # the headline itself
+        vname = f"model_{mname}_p{vpatch[0]}x{vpatch[1]}"
+        mv = m if mname == "B" else mc
         vd, vo = mv.encode(ts, order=nx.WAVEFRONT, patch=vpatch, interleave=args.interleave)
-        vplan, vws = mv.decode_prepare(outs, order=nx.WAVEFRONT, patch=vpatch, interleave=args.interleave)
+        vplan, vws = mv.decode_prepare(outs, order=dec_order, patch=vpatch, interleave=args.interleave)
         mv.decode_run(vplan, vd, vo, status, vws)
         torch.cuda.synchronize()
         ev[0].record(stream)
@@ -248,7 +264,7 @@ def main():
         vh, vC, vnb = (synth.MODEL_DIMS[mname][k] for k in ("h", "C", "n_blocks"))
         vflops = 2 * macs_per_px(vh, vC, vnb) * npx / vstep
         variants[vname] = {"ms": vstep * 1e3, "px_per_s": npx / vstep, "tflops": vflops / 1e12,
-                           "frac_fp32_peak": vflops / PEAK_FP32, "patch": list(vpatch),
+                           "frac_fp32_peak": vflops / PEAK_FP32, "patch": list(vpatch), "layout": args.layout,
                            "model": f"h={vh}, C={vC}, {vnb} block(s)"}
         log(f"[bench] {vname}: decode {vstep * 1e3:.2f} ms ({npx / vstep / 1e6:.0f} Mpx/s, "
             f"{100 * vflops / PEAK_FP32:.1f}% of FP32 peak)")
@@ -377,31 +393,24 @@ def main():
         ends = np.frombuffer(bytes(c0[32:32 + 4 * nl0 * K0]), dtype="<u4").astype(np.int64)
         # bits per lane: the sum of its K stream payloads
         lane_bits = np.diff(np.concatenate([[0], ends])).reshape(nl0, K0).sum(axis=1) * 8
-        lanes_x = 1024 // args.patch
         sample = [0, lanes_x + 3, nl0 - 1]
         ideal = got = 0.0
         for q in sample:
-            ly, lx = divmod(q, lanes_x)
-            crop = imgs[0][ly * args.patch:(ly + 1) * args.patch, lx * args.patch:(lx + 1) * args.patch]
-            ideal += om.stats(np.ascontiguousarray(crop))["qbits"]
+            ideal += om.stats(lane_crop(imgs[0], q))["qbits"]
             got += float(lane_bits[q])
         gap = (got - ideal) / ideal
         log(f"[bench] gap on {len(sample)} lanes: {gap * 100:.4f}% ({got:.0f} vs {ideal:.1f} bits)")
         # oracle CPU decode rate on a bounded sample of the same workload
-        crops = []
-        for q in range(args.cpu_lanes):
-            ly, lx = divmod(q, lanes_x)
-            crops.append(np.ascontiguousarray(
-                imgs[0][ly * args.patch:(ly + 1) * args.patch, lx * args.patch:(lx + 1) * args.patch]))
+        crops = [lane_crop(imgs[0], q) for q in range(args.cpu_lanes)]
         encs = [om.encode(c, 1) for c in crops]
         c0t = time.time()
         for c, enc in zip(crops, encs):
-            dec = om.decode(enc, args.patch, args.patch, 1)
+            dec = om.decode(enc, c.shape[0], c.shape[1], 1)
             assert np.array_equal(dec, c)
         cpu_s = time.time() - c0t
-        cpu = {"value": args.cpu_lanes * args.patch * args.patch / cpu_s, "unit": "decoded px/s", "cores": 1,
+        cpu = {"value": sum(c.shape[0] * c.shape[1] for c in crops) / cpu_s, "unit": "decoded px/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{args.cpu_lanes} {args.patch}x{args.patch} lanes of image 0, wavefront order, "
+               "sample": f"{args.cpu_lanes} {pname} lanes of image 0, wavefront order, "
                          f"FP64 C oracle, 1 thread, {cpu_s:.1f}s"}
         log(f"[bench] oracle CPU: {cpu['value']:.1f} px/s")
 
@@ -485,11 +494,8 @@ def main():
             import oracle
 
             tom = oracle.Model.from_blob(nxblob.blob_from_params(tdims, tp.cpu().numpy()))
-            lanes_x = 1024 // args.patch
-            sample = [0, lanes_x + 3, (1024 // args.patch) ** 2 - 1]
-            crops = [np.ascontiguousarray(imgs[0][(q // lanes_x) * args.patch:(q // lanes_x + 1) * args.patch,
-                                                  (q % lanes_x) * args.patch:(q % lanes_x + 1) * args.patch])
-                     for q in sample]
+            sample = [0, lanes_x + 3, lanes_x * -(-1024 // ph) - 1]
+            crops = [lane_crop(imgs[0], q) for q in sample]
             ideal = sum(tom.stats(c)["qbits"] for c in crops)
             for K in sorted({args.interleave, 1}):
                 dK, oK = mt.encode([ts[0]], order=nx.WAVEFRONT, patch=patch, interleave=K)
@@ -501,7 +507,7 @@ def main():
                 trained_rec[f"gap_vs_oracle_ideal_k{K}"] = (got - ideal) / ideal
                 log(f"[bench] trained model B, {K} stream(s): gap on {len(sample)} lanes "
                     f"{100 * (got - ideal) / ideal:.4f}% ({(got - ideal) / len(sample):.1f} bits per lane)")
-            trained_rec["gap_sample"] = f"lanes {sample} of image 0, {args.patch}x{args.patch}"
+            trained_rec["gap_sample"] = f"lanes {sample} of image 0, {pname} patches"
 
     out = {
         "metric": "decoded pixels/sec on 1 GPU, wavefront+patch vs raster; bits/dim gap vs FP64 oracle",
@@ -519,9 +525,10 @@ def main():
         "config": {
             "workload": "4x1024x1024 + 2x2048x1536 RGB uint8 (smooth field sigma 4, 20 edges, +-3 noise); "
                         "h=3 local model, 64 channels, 2 residual blocks, 10-logistic mixture; "
-                        f"wavefront order, {args.patch}x{args.patch} patches, one rANS lane each "
+                        f"wavefront order, {pname} patches (rows x cols), one rANS lane each "
                         f"with {args.interleave} interleaved stream(s); {args.layout} decoder layout",
             "pixels": npx,
+            "patch": [ph, pw],
             "interleave": args.interleave,
             "layout": args.layout,
         },
@@ -543,7 +550,8 @@ def main():
                                                  f"{'true' if args.layout == 'sheared' else 'false'}>",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "flop_per_px": flops_per_px,
-                     "traffic": decode_traffic_bytes(args.layout), "traffic_unit": "HBM bytes per launch"},
+                     "traffic": decode_traffic_bytes(args.layout, patch, args.interleave),
+                     "traffic_unit": "HBM bytes per launch"},
         "cpu_baseline": cpu,
         "training": train_rec,
         "trained_model": trained_rec,

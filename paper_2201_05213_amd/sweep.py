@@ -104,7 +104,8 @@ def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
         pr(f"| {side} | {tr * 1e3:.2f} ms{rnote} | {tw * 1e3:.2f} ms | {tr / tw:.1f}x | {sp} |")
 
 
-def run_patches(out=sys.stdout, shapes=((32, 64), (64, 64), (128, 64), (64, 128), (128, 128), (96, 96)),
+def run_patches(out=sys.stdout, shapes=((32, 64), (64, 64), (80, 64), (96, 64), (112, 64), (128, 64), (64, 96),
+                                       (64, 128), (96, 96), (128, 128)),
                 streams=(4, 2, 1), reps=3):
     """Decode time of the large batch (4 x 1024^2 + 2 x 2048x1536, model B,
     wavefront order) by patch shape and rANS streams per lane."""

@@ -338,31 +338,36 @@ def test_autotune_patch_and_streams(models, nx):
     assert all(torch.equal(a, b) for a, b in zip(out, ts))
 
 
-def test_large6_full_size_in_bench_configuration(models, nx):
+@pytest.mark.parametrize("patch", [(96, 64), (64, 64)], ids=["p96x64", "p64x64"])
+def test_large6_full_size_in_bench_configuration(models, nx, patch):
     """The large-image workload at full size (4 x 1024^2 + 2 x 2048x1536),
-    model B, wavefront order, 64x64 patches, 4 streams per lane, as the
-    benchmark decodes it: exact round trip of all 10.5 M pixels; sampled
-    lanes within 0.1% of the oracle's quantised ideal; the full CDF rows of
-    sampled lanes within 1 count of the oracle's."""
-    say("[gpu] large6 full size, model B, patch 64, K=4")
+    model B, wavefront order, 4 streams per lane, with the benchmark's 96x64
+    patches (96 rows, 64 columns) and with 64x64 patches: exact round trip of
+    all 10.5 M pixels; sampled lanes within 0.1% of the oracle's quantised
+    ideal; the full CDF rows of a sampled lane within 1 count of the
+    oracle's."""
+    ph, pw = patch
+    say(f"[gpu] large6 full size, model B, patch {ph}x{pw}, K=4")
     m, om, _ = models["B"]
     imgs = synth.workload_images("large6")
     ts = [cuda(i) for i in imgs]
-    data, offs = m.encode(ts, order=1, patch=(64, 64), interleave=4)
-    out, st = m.decode(data, offs, [i.shape[:2] for i in imgs], order=1, patch=(64, 64), interleave=4)
+    data, offs = m.encode(ts, order=1, patch=patch, interleave=4)
+    out, st = m.decode(data, offs, [i.shape[:2] for i in imgs], order=1, patch=patch, interleave=4)
     for a, b in zip(out, ts):
         assert torch.equal(a, b)
-    # lane payloads of image 4 (2048 x 1536: 32 x 24 lanes)
+    # lane payloads of image 4 (2048 x 1536: 24 lanes across; the last lane
+    # row of the 96-row patches is 32 rows tall)
     d = data.cpu().numpy()
     o = offs.cpu().numpy()
     c = d[o[4]:o[5]]
     nl, K = int.from_bytes(bytes(c[28:32]), "little"), int(c[7])
+    assert nl == 24 * -(-2048 // ph)
     ends = np.frombuffer(bytes(c[32:32 + 4 * nl * K]), dtype="<u4").astype(np.int64)
     lane_bits = np.diff(np.concatenate([[0], ends])).reshape(nl, K).sum(axis=1) * 8
     got = ideal = 0.0
     for q in (0, 24 * 5 + 7, nl - 1):
         ly, lx = divmod(q, 24)
-        crop = np.ascontiguousarray(imgs[4][64 * ly:64 * ly + 64, 64 * lx:64 * lx + 64])
+        crop = np.ascontiguousarray(imgs[4][ph * ly:ph * ly + ph, pw * lx:pw * lx + pw])
         ideal += om.stats(crop)["qbits"]
         got += float(lane_bits[q])
         # a patch is coded as an image of its own: its CDF rows are those of the crop

@@ -223,15 +223,16 @@ def test_edges_and_errors(nx):
 
 def test_full_size_batch(nx):
     """The benchmark's batch shape (4 x 1024^2 + 2 x 2048x1536, model B,
-    64x64 patches, wavefront): every symbol against the GPU's own CDF, a few
+    96x64 patches, wavefront): every symbol against the GPU's own CDF, a few
     patches against the oracle, and the sample coded and decoded back."""
-    say("[gpu] sample: full-size batch, model B, patch 64")
+    say("[gpu] sample: full-size batch, model B, patch 96x64")
     m, om = models(nx, "B")
     shapes = synth.workload_shapes("large6")
     seeds = [900 + k for k in range(len(shapes))]
-    out = m.sample(shapes, seeds, patch=(64, 64))
+    ph, pw = 96, 64
+    out = m.sample(shapes, seeds, patch=(ph, pw))
     torch.cuda.synchronize()
-    check_inverse_cdf(m, out, seeds, (64, 64))
+    check_inverse_cdf(m, out, seeds, (ph, pw))
     say("  inverse-CDF property holds on every symbol")
     rng = np.random.Generator(np.random.PCG64(4))
     n_bad = n_syms = 0
@@ -239,15 +240,15 @@ def test_full_size_batch(nx):
         H, W = shapes[k]
         full = host(out[k])
         for _ in range(2):
-            py = int(rng.integers(0, (H + 63) // 64)) * 64
-            px = int(rng.integers(0, (W + 63) // 64)) * 64
-            crop = np.ascontiguousarray(full[py:py + 64, px:px + 64])
+            py = int(rng.integers(0, -(-H // ph))) * ph
+            px = int(rng.integers(0, -(-W // pw))) * pw
+            crop = np.ascontiguousarray(full[py:py + ph, px:px + pw])
             v, cdf, slot = oracle_choice(om, crop, seeds[k], 0, 0, W_full=W, y0=py, x0=px)
             n_bad += explained(crop, v, cdf, slot)
             n_syms += crop.size
     say(f"  oracle patches: {n_syms} symbols, {n_bad} on a one-count boundary")
     assert n_bad <= max(1, n_syms // 10000)
-    data, offs = m.encode(out, patch=(64, 64), interleave=4)
-    back, _ = m.decode(data, offs, shapes, patch=(64, 64), interleave=4)
+    data, offs = m.encode(out, patch=(ph, pw), interleave=4)
+    back, _ = m.decode(data, offs, shapes, patch=(ph, pw), interleave=4)
     for a, b in zip(out, back):
         assert torch.equal(a, b)
