@@ -223,13 +223,16 @@ def test_edges_and_errors(nx):
 
 def test_full_size_batch(nx):
     """The benchmark's batch shape (4 x 1024^2 + 2 x 2048x1536, model B,
-    96x64 patches, wavefront): every symbol against the GPU's own CDF, a few
-    patches against the oracle, and the sample coded and decoded back."""
-    say("[gpu] sample: full-size batch, model B, patch 96x64")
+    the benchmark's patches, wavefront): every symbol against the GPU's own
+    CDF, a few patches against the oracle, and the sample coded and decoded
+    back."""
+    from paper_2201_05213_amd import tune
+
     m, om = models(nx, "B")
     shapes = synth.workload_shapes("large6")
     seeds = [900 + k for k in range(len(shapes))]
-    ph, pw = 96, 64
+    ph, pw = tune.balanced_patch(shapes)
+    say(f"[gpu] sample: full-size batch, model B, patch {ph}x{pw}")
     out = m.sample(shapes, seeds, patch=(ph, pw))
     torch.cuda.synchronize()
     check_inverse_cdf(m, out, seeds, (ph, pw))

@@ -100,15 +100,18 @@ def test_sheared_decode_vs_oracle_algorithm2(nx, patch):
 
 
 def test_sheared_full_size(nx):
-    """The benchmark configuration: 4 x 1024^2 + 2 x 2048x1536, model B,
-    96x64 patches (96 rows, 64 columns), four streams, decoded in the sheared
-    layout."""
+    """The benchmark configuration: 4 x 1024^2 + 2 x 2048x1536, model B, the
+    benchmark's patches (tune.balanced_patch), four streams, decoded in the
+    sheared layout."""
+    from paper_2201_05213_amd import tune
+
     say("[gpu] sheared decode: full-size batch")
     m, _ = models(nx, "B")
     ts = [cuda(i) for i in synth.workload_images("large6")]
     shapes = [tuple(t.shape[:2]) for t in ts]
-    data, offs = m.encode(ts, order=nx.WAVEFRONT, patch=(96, 64), interleave=4)
-    out, st = m.decode(data, offs, shapes, order=nx.SHEARED, patch=(96, 64), interleave=4)
+    patch = tune.balanced_patch(shapes)
+    data, offs = m.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=4)
+    out, st = m.decode(data, offs, shapes, order=nx.SHEARED, patch=patch, interleave=4)
     assert int(st.abs().sum()) == 0
     for a, b in zip(out, ts):
         assert torch.equal(a, b)
