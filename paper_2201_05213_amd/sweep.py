@@ -7,6 +7,7 @@ random-init local models with h = 3.
 
     python -m paper_2201_05213_amd.sweep > table.md
     python -m paper_2201_05213_amd.sweep --patches   # large batch: patch shape x streams
+    python -m paper_2201_05213_amd.sweep --patches --shapes 84x64,86x64 --streams 4
 """
 from __future__ import annotations
 
@@ -136,8 +137,14 @@ if __name__ == "__main__":
     ap.add_argument("--raster-rows", type=int, default=8)
     ap.add_argument("--patches", action="store_true",
                     help="instead: decode time of the large batch by patch shape and streams per lane")
+    ap.add_argument("--shapes", default=None,
+                    help="with --patches: comma-separated ROWSxCOLS patch shapes (default: a fixed set)")
+    ap.add_argument("--streams", default="4,2,1", help="with --patches: comma-separated streams per lane")
     a = ap.parse_args()
     if a.patches:
-        run_patches()
+        kw = {"streams": tuple(int(k) for k in a.streams.split(","))}
+        if a.shapes:
+            kw["shapes"] = tuple(tuple(int(v) for v in sh.split("x")) for sh in a.shapes.split(","))
+        run_patches(**kw)
     else:
         run(a.channels, a.raster_rows)
