@@ -447,7 +447,7 @@ def main():
         pool = torch.from_numpy(synth.training_pool(n=512)).to(dev)
         rng = np.random.Generator(np.random.PCG64(5_999_999))
         p = torch.nn.Parameter(torch.from_numpy(tparams).to(dev))
-        opt = torch.optim.Adam([p], lr=1e-3)
+        opt = torch.optim.Adam([p], lr=1e-3, fused=True)
         batches = [nxtrain.random_crops(pool, 64, 32, rng) for _ in range(args.train_steps + 5)]
 
         def train_step(x):

@@ -8,7 +8,7 @@ tensor order; `blob.params_from_blob` / `blob.blob_from_params` convert.
 
     dims = (h, C, n_blocks, 10)
     p = torch.nn.Parameter(torch.from_numpy(params).cuda())
-    opt = torch.optim.Adam([p], lr=1e-3)
+    opt = torch.optim.Adam([p], lr=1e-3, fused=True)
     bits = nll_bits(p, dims, crops)          # crops: (N, H, W, 3) uint8 on the GPU
     (bits.sum() / crops[..., 0].numel() / 3).backward(); opt.step()
 """
@@ -108,7 +108,8 @@ def fit(params: torch.Tensor, dims, pool: torch.Tensor, steps: int, rng, batch: 
     parameter vector (a new tensor). on_step(step, loss_tensor) is called
     after every step if given."""
     p = torch.nn.Parameter(params.detach().clone())
-    opt = torch.optim.Adam([p], lr=lr)
+    # one parameter tensor: the fused update is one kernel per step
+    opt = torch.optim.Adam([p], lr=lr, fused=True)
     for step in range(steps):
         x = random_crops(pool, batch, crop, rng)
         opt.zero_grad(set_to_none=True)
