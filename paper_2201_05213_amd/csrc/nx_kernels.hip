@@ -157,48 +157,173 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
 }
 
 // ------------------------------------------------------------------ rANS encoder
-// one thread per stream (lane L, stream k): stream index L K + k
-__global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
-  const int64_t SL = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (SL >= A.n_lanes * A.K) return;
+// Two kernels. A stream's states are one serial chain, run by one thread,
+// and with a few thousand streams a wave has a SIMD to itself: its time per
+// symbol is its own instruction count. So the walk over the stream's
+// symbols in reverse decode order, and their addresses and loads, come out
+// of that chain into k_rans_gather, which writes every stream's symbols
+// contiguously, many threads per stream (each a range of wavefront steps);
+// k_rans_enc then reads them in order and codes.
+
+// lane geometry of stream SL = L K + kk
+struct StreamGeom {
+  ImgDesc D;
+  int kk, q, y0, x0, Hl, Wl;
+  int64_t lane_px_off;
+};
+NXD StreamGeom stream_geom(const RansEncArgs& A, int64_t SL) {
+  StreamGeom G;
   const int64_t L = SL / A.K;
-  const int kk = (int)(SL - L * A.K);
+  G.kk = (int)(SL - L * A.K);
   const int n = find_img(A.desc, A.n_img, L, true);
-  const ImgDesc D = A.desc[n];
-  const int q = (int)(L - D.lane_base);
-  const int ly = q / D.nlx, lx = q - ly * D.nlx;
-  const int y0 = ly * D.ph, x0 = lx * D.pw;
-  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - x0);
-  const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
-  const int64_t slot_end = D.slot_base + A.K * (6 * lane_px_off + 8 * (int64_t)q) +
-                           (kk + 1) * lane_slot_bytes((int64_t)Hl * Wl);
-  uint8_t* out = A.slots + slot_end;
-  const uint32_t* sym = A.sym + D.px_base * 3;
+  G.D = A.desc[n];
+  G.q = (int)(L - G.D.lane_base);
+  const int ly = G.q / G.D.nlx, lx = G.q - ly * G.D.nlx;
+  G.y0 = ly * G.D.ph;
+  G.x0 = lx * G.D.pw;
+  G.Hl = min(G.D.ph, G.D.H - G.y0);
+  G.Wl = min(G.D.pw, G.D.W - G.x0);
+  G.lane_px_off = (int64_t)ly * G.D.ph * G.D.W + (int64_t)lx * G.D.pw * G.Hl;
+  return G;
+}
+
+constexpr int GATHER_SEGS = 32;  // threads per stream in k_rans_gather (half a wave)
+
+// Thread (stream, seg) = lane seg of the stream's half-wave: segment seg of
+// the stream's wavefront steps, [T seg / S, T (seg + 1) / S). In coding
+// order the later steps come first, so the segment starts after the symbols
+// of segments seg + 1 .. S - 1: a suffix sum of the per-segment counts
+// across the half-wave. The total (segment 0's inclusive sum) is the
+// stream's length. Raster order (one stream): equal ranges of the reversed
+// raster index.
+template <int O, int K>
+__global__ void __launch_bounds__(64) k_rans_gather(RansEncArgs A) {
+  const int64_t NS = A.n_lanes * K;
+  const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t SL = gid / GATHER_SEGS;
+  const int seg = (int)(gid - SL * GATHER_SEGS);
+  const bool live = SL < NS;
+  StreamGeom G{};
+  int T = 0, tlo = 0, thi = 0, cnt = 0;
+  if (live) {
+    G = stream_geom(A, SL);
+    if (A.order != 0) {
+      T = G.Wl + O * (G.Hl - 1);
+      tlo = (int)((int64_t)T * seg / GATHER_SEGS);
+      thi = (int)((int64_t)T * (seg + 1) / GATHER_SEGS);
+      for (int t = tlo; t < thi; ++t) cnt += 3 * stream_rows_at(t, G.Hl, G.Wl, O, K, G.kk);
+    }
+  }
+  // inclusive suffix sum over the half-wave (every lane takes part)
+  int suf = cnt;
+#pragma unroll
+  for (int d = 1; d < GATHER_SEGS; d <<= 1) {
+    const int v = __shfl_down(suf, d, GATHER_SEGS);
+    if (seg + d < GATHER_SEGS) suf += v;
+  }
+  if (!live) return;
+  const uint32_t* sym = A.sym + G.D.px_base * 3;
+  uint32_t* dst = A.rev + SL * A.rev_cap;
+  if (A.order == 0) {
+    const int64_t N = 3LL * G.Hl * G.Wl;
+    const int64_t b = N * seg / GATHER_SEGS, e = N * (seg + 1) / GATHER_SEGS;
+    for (int64_t p = b; p < e; ++p) {  // consecutive in the image row: loads pipeline
+      const int64_t f = N - 1 - p;
+      const int i = (int)(f / (3LL * G.Wl));
+      const int r = (int)(f - (int64_t)i * 3 * G.Wl);
+      const int j = r / 3;
+      if (p < A.rev_cap) dst[p] = sym[((int64_t)(G.y0 + i) * G.D.W + (G.x0 + j)) * 3 + (r - 3 * j)];
+    }
+    if (seg == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(N, A.rev_cap);
+    return;
+  }
+  int64_t pos = suf - cnt;
   RevOrder it;
-  it.init(Hl, Wl, A.h + 1, A.order == 0, A.K, kk);
-  uint32_t x = RANS_X0;
-  constexpr int B = 16;  // symbols fetched per batch (independent loads in flight)
+  it.init_steps(G.Hl, G.Wl, O, K, G.kk, tlo, thi);
+  // 16 independent loads in flight, then their stores
+  constexpr int B = 16;
   while (!it.done) {
     uint32_t v[B];
     int nv = 0;
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       if (!it.done) {
-        const int64_t idx = ((int64_t)(y0 + it.i) * D.W + (x0 + it.col())) * 3 + it.c;
-        v[k] = sym[idx];
+        v[k] = sym[((int64_t)(G.y0 + it.i) * G.D.W + (G.x0 + it.col())) * 3 + it.c];
         ++nv;
         it.advance();
       }
     }
-    for (int k = 0; k < nv; ++k) {
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (k < nv && pos + k < A.rev_cap) dst[pos + k] = v[k];
+    pos += nv;
+  }
+  if (seg == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(suf, A.rev_cap);
+}
+
+// rANS-encodes n symbols (start | freq << 16) into state x, bytes written
+// backwards at out. x / f: a float quotient (relative error below 2^-21, so
+// within one of the true one, as x / f < 2^15 after renormalisation) fixed
+// by one step of the remainder; a state below 2^31 sheds at most two bytes.
+template <int B>
+__device__ __forceinline__ void rans_put(uint32_t& x, uint8_t*& out, const uint32_t (&v)[B], int n) {
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    if (k < n) {
       const uint32_t s = v[k] & 0xffffu, f = v[k] >> 16;
+      const float rf = __builtin_amdgcn_rcpf((float)f);
       const uint32_t xmax = ((RANS_L >> CDF_BITS) << 8) * f;
-      while (x >= xmax) {
-        *--out = (uint8_t)(x & 255u);
-        x >>= 8;
+      const uint32_t b1 = x >= xmax ? 1u : 0u;
+      const uint32_t b2 = (x >> 8) >= xmax ? 1u : 0u;
+      if (b1) out[-1] = (uint8_t)x;
+      if (b2) out[-2] = (uint8_t)(x >> 8);
+      out -= b1 + b2;
+      x >>= 8u * (b1 + b2);
+      uint32_t qt = (uint32_t)((float)x * rf);
+      int32_t r = (int32_t)(x - qt * f);
+      if (r < 0) {
+        --qt;
+        r += (int32_t)f;
+      } else if (r >= (int32_t)f) {
+        ++qt;
+        r -= (int32_t)f;
       }
-      x = ((x / f) << CDF_BITS) + (x % f) + s;
+      x = (qt << CDF_BITS) + (uint32_t)r + s;
     }
+  }
+}
+
+// one thread per stream (lane L, stream k): stream index L K + k
+__global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
+  const int64_t SL = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (SL >= A.n_lanes * A.K) return;
+  const StreamGeom G = stream_geom(A, SL);
+  const int64_t slot_end = G.D.slot_base + A.K * (6 * G.lane_px_off + 8 * (int64_t)G.q) +
+                           (G.kk + 1) * lane_slot_bytes((int64_t)G.Hl * G.Wl);
+  uint8_t* out = A.slots + slot_end;
+  const uint4* src = (const uint4*)(A.rev + SL * A.rev_cap);
+  const int64_t n = A.lane_len[SL];
+  uint32_t x = RANS_X0;
+  constexpr int B = 16;  // symbols per batch; the next batch loads while this one is coded
+  uint32_t va[B], vb[B];
+  int na = 0;
+  for (int64_t p0 = 0;; p0 += B) {
+    const int nb = p0 < n ? (int)min<int64_t>(B, n - p0) : 0;
+    if (nb > 0) {
+#pragma unroll
+      for (int k = 0; k < B / 4; ++k) {
+        const uint4 w = src[p0 / 4 + k];
+        vb[4 * k] = w.x;
+        vb[4 * k + 1] = w.y;
+        vb[4 * k + 2] = w.z;
+        vb[4 * k + 3] = w.w;
+      }
+    }
+    if (na > 0) rans_put(x, out, va, na);
+    if (nb == 0) break;
+#pragma unroll
+    for (int k = 0; k < B; ++k) va[k] = vb[k];
+    na = nb;
   }
   out -= 4;
   out[0] = (uint8_t)x;
@@ -1017,8 +1142,30 @@ hipError_t launch_sample(int h, int C, const DecArgs& a, int grid, int waves, hi
   NX_DISPATCH(sample_t, h, C, a, grid, waves, s);
 }
 
+template <int O, int K>
+static void launch_gather(const RansEncArgs& a, hipStream_t s) {
+  const int64_t grid = (a.n_lanes * K * GATHER_SEGS + 63) / 64;
+  hipLaunchKernelGGL((k_rans_gather<O, K>), dim3((unsigned)grid), dim3(64), 0, s, a);
+}
+
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
+  if (a.h < 1 || a.h > 3 || (a.K != 1 && a.K != 2 && a.K != 4) || (a.rev_cap & 15) != 0)
+    return hipErrorInvalidValue;
+  const int sel = 3 * (a.h - 1) + (a.K == 1 ? 0 : a.K == 2 ? 1 : 2);
+  switch (sel) {
+    case 0: launch_gather<2, 1>(a, s); break;
+    case 1: launch_gather<2, 2>(a, s); break;
+    case 2: launch_gather<2, 4>(a, s); break;
+    case 3: launch_gather<3, 1>(a, s); break;
+    case 4: launch_gather<3, 2>(a, s); break;
+    case 5: launch_gather<3, 4>(a, s); break;
+    case 6: launch_gather<4, 1>(a, s); break;
+    case 7: launch_gather<4, 2>(a, s); break;
+    default: launch_gather<4, 4>(a, s); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int grid = (int)((a.n_lanes * a.K + 63) / 64);
   hipLaunchKernelGGL(k_rans_enc, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();

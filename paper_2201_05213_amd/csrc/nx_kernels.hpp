@@ -36,7 +36,9 @@ struct RansEncArgs {
   int K;                   // rANS streams per lane
   const uint32_t* sym;
   uint8_t* slots;
-  uint32_t* lane_len;
+  uint32_t* lane_len;      // symbols per stream (gather), then bytes per stream (encoder)
+  uint32_t* rev;           // per stream, its symbols in coding order (reverse decode order)
+  int64_t rev_cap;         // words per stream in rev, a multiple of 16
 };
 
 struct PackArgs {

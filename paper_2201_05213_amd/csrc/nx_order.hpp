@@ -15,6 +15,17 @@ NXHD void step_rows(int t, int Hl, int Wl, int o, int& ilo, int& ihi) {
   ihi = nx_min(Hl - 1, t / o);
 }
 
+// rows of stream kk (of K, K dividing 16) at wavefront step t: a full group
+// of 16 rows gives each stream 16 / K of them, a partial group of r rows the
+// offsets kk, kk + K, ... below r
+NXHD int stream_rows_at(int t, int Hl, int Wl, int o, int K, int kk) {
+  int ilo, ihi;
+  step_rows(t, Hl, Wl, o, ilo, ihi);
+  if (ilo > ihi) return 0;
+  const int n = ihi - ilo + 1, full = n / 16, rem = n - 16 * full;
+  return full * (16 / K) + (rem > kk ? (rem - kk + K - 1) / K : 0);
+}
+
 // Symbols of a lane in decode order:
 //   wavefront: steps t ascending; within a step the active rows are cut into
 //   groups of 16 consecutive rows; per group channels R, G, B; per channel
@@ -26,6 +37,7 @@ NXHD void step_rows(int t, int Hl, int Wl, int o, int& ilo, int& ihi) {
 struct RevOrder {
   int Hl, Wl, o, raster, K, kk;
   int t, ilo, ihi, ts, te, c, i;
+  int tstop;  // the walk ends below this step
   bool done;
 
   // highest row of stream kk in rows [ts, te], or ts - 1 if it has none
@@ -39,7 +51,7 @@ struct RevOrder {
     for (;;) {
       step_rows(t, Hl, Wl, o, ilo, ihi);
       if (ilo <= ihi) break;
-      if (--t < 0) { done = true; return; }
+      if (--t < tstop) { done = true; return; }
     }
     ts = ilo + ((ihi - ilo) / 16) * 16;
     te = nx_min(ts + 15, ihi);
@@ -52,14 +64,22 @@ struct RevOrder {
       if (--c >= 0) { i = top_row(); continue; }
       ts -= 16;
       if (ts >= ilo) { te = ts + 15; c = 2; i = top_row(); continue; }
-      if (--t < 0) { done = true; return; }
+      if (--t < tstop) { done = true; return; }
       enter_step();
     }
   }
   NXHD void init(int Hl_, int Wl_, int o_, int raster_, int K_, int kk_) {
-    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; K = K_; kk = kk_; done = false;
+    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; K = K_; kk = kk_; done = false; tstop = 0;
     if (raster) { i = Hl - 1; j = Wl - 1; c = 2; return; }
     t = Wl + o * (Hl - 1) - 1;
+    enter_step();
+    settle();
+  }
+  // the wavefront walk over steps t_hi - 1 down to t_lo only (t_lo <= t_hi)
+  NXHD void init_steps(int Hl_, int Wl_, int o_, int K_, int kk_, int t_lo, int t_hi) {
+    Hl = Hl_; Wl = Wl_; o = o_; raster = 0; K = K_; kk = kk_; done = false; tstop = t_lo;
+    t = t_hi - 1;
+    if (t < tstop) { done = true; return; }
     enter_step();
     settle();
   }

@@ -113,3 +113,72 @@ def test_encoder_walk_reverses_decoder_order(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout
     assert " 0 bad" in r.stdout
+
+
+SEG_DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include <tuple>
+#include "nx_order.hpp"
+using namespace nx;
+typedef std::tuple<int, int, int> Sym;
+
+static std::vector<Sym> walk(RevOrder it) {
+  std::vector<Sym> v;
+  while (!it.done) { v.push_back(Sym(it.i, it.col(), it.c)); it.advance(); }
+  return v;
+}
+
+int main() {
+  int cases = 0, bad = 0;
+  for (int h = 1; h <= 3; ++h)
+    for (int K : {1, 2, 4})
+      for (int Hl = 1; Hl <= 90; Hl += (Hl < 6 ? 1 : 13))
+        for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13))
+          for (int kk = 0; kk < K; ++kk) {
+            ++cases;
+            const int o = h + 1, T = Wl + o * (Hl - 1);
+            RevOrder full;
+            full.init(Hl, Wl, o, 0, K, kk);
+            const std::vector<Sym> ref = walk(full);
+            long total = 0;
+            for (int t = 0; t < T; ++t) total += 3 * stream_rows_at(t, Hl, Wl, o, K, kk);
+            if (total != (long)ref.size()) { ++bad; if (bad < 5) printf("count h%d K%d %dx%d kk%d: %ld vs %zu\n", h, K, Hl, Wl, kk, total, ref.size()); }
+            for (int S : {1, 3, 8, 32}) {
+              std::vector<Sym> cat;
+              for (int seg = S - 1; seg >= 0; --seg) {
+                const int lo = (int)((long)T * seg / S), hi = (int)((long)T * (seg + 1) / S);
+                long pos = 0;
+                for (int t = hi; t < T; ++t) pos += 3 * stream_rows_at(t, Hl, Wl, o, K, kk);
+                if (pos != (long)cat.size()) { ++bad; if (bad < 5) printf("pos h%d K%d %dx%d kk%d S%d seg%d\n", h, K, Hl, Wl, kk, S, seg); }
+                RevOrder it;
+                it.init_steps(Hl, Wl, o, K, kk, lo, hi);
+                const std::vector<Sym> part = walk(it);
+                cat.insert(cat.end(), part.begin(), part.end());
+              }
+              if (cat != ref) { ++bad; if (bad < 5) printf("walk h%d K%d %dx%d kk%d S%d\n", h, K, Hl, Wl, kk, S); }
+            }
+          }
+  printf("%d cases, %d bad\n", cases, bad);
+  return bad != 0;
+}
+"""
+
+
+def test_segmented_walks_and_step_counts(tmp_path):
+    """The encoder's gather splits each stream's reverse walk into step
+    ranges: walks over consecutive ranges (highest first) concatenate to the
+    full walk, and each range starts at the position given by the per-step
+    stream counts (stream_rows_at) of the steps after it, whose total is the
+    stream's length."""
+    src = tmp_path / "seg.cpp"
+    exe = tmp_path / "seg"
+    src.write_text(SEG_DRIVER)
+    cmd = ["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I", "/opt/rocm/include",
+           str(src), "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail("host build of nx_order.hpp failed:\n" + r.stderr[-2000:])
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout
+    assert " 0 bad" in r.stdout
