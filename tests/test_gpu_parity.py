@@ -445,3 +445,25 @@ def test_maximum_sides(models, nx, shape, patch, orders):
         start, freq = (s & 0xFFFF).astype(np.int64), (s >> 16).astype(np.int64)
         slot = numpy_slots(99, H, W)
         assert np.all(start <= slot) and np.all(slot < start + freq)
+
+
+def test_balanced_patch_launch_shape(models, nx):
+    """tune.balanced_patch's claim against the decoder's own launch plan:
+    with the chosen patch the large batch fits the persistent launch in one
+    round with at most two lanes per SIMD (at most 8 waves per workgroup, one
+    workgroup per CU), in both decoder layouts. (That no shorter height
+    qualifies is a host test.)"""
+    from paper_2201_05213_amd import tune
+
+    m, _, _ = models["B"]
+    shapes = synth.workload_shapes("large6")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    patch = tune.balanced_patch(shapes)
+    say(f"[gpu] balanced patch on {cus} CUs: {patch}")
+    for order in (nx.WAVEFRONT, nx.SHEARED):
+        out = [torch.empty((H, W, 3), dtype=torch.uint8, device="cuda") for H, W in shapes]
+        plan, ws = m.decode_prepare(out, order=order, patch=patch, interleave=4)
+        assert plan.n_lanes == tune.lane_count(shapes, patch)
+        assert plan.waves <= 8 and plan.grid <= cus
+        assert plan.n_lanes <= plan.grid * plan.waves  # every lane in flight at once
+        del ws
