@@ -34,10 +34,10 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # 256 MiB device copy, per decoder layout; valid only for the kernel sources,
 # patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "sheared": {"src_sha": "28c59b6e2ac94f74", "patch": (86, 64), "interleave": 4,
-                "fetch_kib": 27506.1, "write_kib": 553729.9, "fetch_scale": 1.99981, "write_scale": 1.0},
-    "unsheared": {"src_sha": "28c59b6e2ac94f74", "patch": (86, 64), "interleave": 4,
-                  "fetch_kib": 37834.2, "write_kib": 32074.3, "fetch_scale": 1.99981, "write_scale": 1.0},
+    "sheared": {"src_sha": "b35992e3b57d4f18", "patch": (86, 64), "interleave": 4,
+                "fetch_kib": 27520.8, "write_kib": 555196.7, "fetch_scale": 1.99981, "write_scale": 1.0},
+    "unsheared": {"src_sha": "b35992e3b57d4f18", "patch": (86, 64), "interleave": 4,
+                  "fetch_kib": 38416.2, "write_kib": 32044.4, "fetch_scale": 1.99981, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 

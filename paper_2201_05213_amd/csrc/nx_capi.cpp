@@ -103,7 +103,9 @@ struct Plan {
   int order = 0;   // 0 raster, 1 wavefront, 2 wavefront decoded in the sheared layout
   int ph_max = 0;  // tallest lane of the batch
   int64_t ring_waves = 0, ring_rows = 0;  // sheared context rings (set by plan_ring)
-  int64_t rev_cap = 0;  // words per rANS stream for the encoder's gathered symbols
+  int64_t rev_cap = 0;    // words per rANS stream for the encoder's symbols in coding order
+  int64_t after_cap = 0;  // entries per stream of the encoder's per-step offsets
+  int64_t max_lane_px = 0;
 };
 
 // the coded order of a request: the sheared layout codes the wavefront order
@@ -149,12 +151,14 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     // 3 (ph pw / K + T) symbols, T = pw + (h + 1)(ph - 1) steps, h + 1 <= 4
     const int64_t cap = 3 * (((int64_t)D.ph * D.pw + P.K - 1) / P.K + D.pw + 4 * ((int64_t)D.ph - 1));
     P.rev_cap = std::max(P.rev_cap, (cap + 15) / 16 * 16);
+    P.after_cap = std::max(P.after_cap, (int64_t)D.pw + 4 * ((int64_t)D.ph - 1) + 1);
+    P.max_lane_px = std::max(P.max_lane_px, (int64_t)D.ph * D.pw);
   }
   return NELLOX_OK;
 }
 
 struct WsLayout {
-  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, ring, rev, total;
+  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, ring, rev, after, total;
 };
 
 WsLayout ws_layout(const Plan& P, int n) {
@@ -171,6 +175,7 @@ WsLayout ws_layout(const Plan& P, int n) {
   W.sym = o; o = align256(o + 12 * std::max<int64_t>(P.n_px, 1));
   W.slots = o; o = align256(o + std::max<int64_t>(P.slot_bytes, 1));
   W.rev = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K * P.rev_cap, 1));
+  W.after = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K * P.after_cap, 1));
   W.total = o;
   return W;
 }
@@ -457,6 +462,9 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   r.lane_len = (uint32_t*)(w8 + W.lane_len);
   r.rev = (uint32_t*)(w8 + W.rev);
   r.rev_cap = P.rev_cap;
+  r.after = (int32_t*)(w8 + W.after);
+  r.after_cap = P.after_cap;
+  r.max_lane_px = P.max_lane_px;
   hipError_t e = launch_rans_encode(r, s);
   if (e != hipSuccess) return hip_fail(e, "rANS encoder launch");
   PackArgs pk{};

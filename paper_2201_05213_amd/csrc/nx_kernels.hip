@@ -157,12 +157,12 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
 }
 
 // ------------------------------------------------------------------ rANS encoder
-// Two kernels. A stream's states are one serial chain, run by one thread,
+// Three kernels. A stream's states are one serial chain, run by one thread,
 // and with a few thousand streams a wave has a SIMD to itself: its time per
 // symbol is its own instruction count. So the walk over the stream's
-// symbols in reverse decode order, and their addresses and loads, come out
-// of that chain into k_rans_gather, which writes every stream's symbols
-// contiguously, many threads per stream (each a range of wavefront steps);
+// symbols in reverse decode order, and their loads, come out of that chain:
+// k_rans_counts and k_rans_scatter lay every stream's symbols out
+// contiguously in coding order, reading the symbol buffer in pixel order;
 // k_rans_enc then reads them in order and codes.
 
 // lane geometry of stream SL = L K + kk
@@ -187,78 +187,74 @@ NXD StreamGeom stream_geom(const RansEncArgs& A, int64_t SL) {
   return G;
 }
 
-constexpr int GATHER_SEGS = 32;  // threads per stream in k_rans_gather (half a wave)
-
-// Thread (stream, seg) = lane seg of the stream's half-wave: segment seg of
-// the stream's wavefront steps, [T seg / S, T (seg + 1) / S). In coding
-// order the later steps come first, so the segment starts after the symbols
-// of segments seg + 1 .. S - 1: a suffix sum of the per-segment counts
-// across the half-wave. The total (segment 0's inclusive sum) is the
-// stream's length. Raster order (one stream): equal ranges of the reversed
-// raster index.
+// One wave per stream. Each lane counts the stream's symbols in a range of
+// wavefront steps (stream_rows_at); a suffix sum across the wave gives the
+// symbols after each range; the lane then writes, per step t of its range,
+// how many of the stream's symbols come in steps after t (in coding order
+// the later steps come first). Lane 0's inclusive sum is the stream's
+// length. Raster order: the length only.
 template <int O, int K>
-__global__ void __launch_bounds__(64) k_rans_gather(RansEncArgs A) {
-  const int64_t NS = A.n_lanes * K;
-  const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int64_t SL = gid / GATHER_SEGS;
-  const int seg = (int)(gid - SL * GATHER_SEGS);
-  const bool live = SL < NS;
-  StreamGeom G{};
-  int T = 0, tlo = 0, thi = 0, cnt = 0;
-  if (live) {
-    G = stream_geom(A, SL);
-    if (A.order != 0) {
-      T = G.Wl + O * (G.Hl - 1);
-      tlo = (int)((int64_t)T * seg / GATHER_SEGS);
-      thi = (int)((int64_t)T * (seg + 1) / GATHER_SEGS);
-      for (int t = tlo; t < thi; ++t) cnt += 3 * stream_rows_at(t, G.Hl, G.Wl, O, K, G.kk);
-    }
-  }
-  // inclusive suffix sum over the half-wave (every lane takes part)
-  int suf = cnt;
-#pragma unroll
-  for (int d = 1; d < GATHER_SEGS; d <<= 1) {
-    const int v = __shfl_down(suf, d, GATHER_SEGS);
-    if (seg + d < GATHER_SEGS) suf += v;
-  }
-  if (!live) return;
-  const uint32_t* sym = A.sym + G.D.px_base * 3;
-  uint32_t* dst = A.rev + SL * A.rev_cap;
+__global__ void __launch_bounds__(64) k_rans_counts(RansEncArgs A) {
+  const int64_t SL = blockIdx.x;
+  const int lane = (int)threadIdx.x;
+  const StreamGeom G = stream_geom(A, SL);
   if (A.order == 0) {
-    const int64_t N = 3LL * G.Hl * G.Wl;
-    const int64_t b = N * seg / GATHER_SEGS, e = N * (seg + 1) / GATHER_SEGS;
-    for (int64_t p = b; p < e; ++p) {  // consecutive in the image row: loads pipeline
-      const int64_t f = N - 1 - p;
-      const int i = (int)(f / (3LL * G.Wl));
-      const int r = (int)(f - (int64_t)i * 3 * G.Wl);
-      const int j = r / 3;
-      if (p < A.rev_cap) dst[p] = sym[((int64_t)(G.y0 + i) * G.D.W + (G.x0 + j)) * 3 + (r - 3 * j)];
-    }
-    if (seg == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(N, A.rev_cap);
+    if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(3LL * G.Hl * G.Wl, A.rev_cap);
     return;
   }
-  int64_t pos = suf - cnt;
-  RevOrder it;
-  it.init_steps(G.Hl, G.Wl, O, K, G.kk, tlo, thi);
-  // 16 independent loads in flight, then their stores
-  constexpr int B = 16;
-  while (!it.done) {
-    uint32_t v[B];
-    int nv = 0;
+  const int T = G.Wl + O * (G.Hl - 1);
+  const int tlo = (int)((int64_t)T * lane / 64), thi = (int)((int64_t)T * (lane + 1) / 64);
+  int cnt = 0;
+  for (int t = tlo; t < thi; ++t) cnt += 3 * stream_rows_at(t, G.Hl, G.Wl, O, K, G.kk);
+  int suf = cnt;
 #pragma unroll
-    for (int k = 0; k < B; ++k) {
-      if (!it.done) {
-        v[k] = sym[((int64_t)(G.y0 + it.i) * G.D.W + (G.x0 + it.col())) * 3 + it.c];
-        ++nv;
-        it.advance();
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < B; ++k)
-      if (k < nv && pos + k < A.rev_cap) dst[pos + k] = v[k];
-    pos += nv;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_down(suf, d, 64);
+    if (lane + d < 64) suf += v;
   }
-  if (seg == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(suf, A.rev_cap);
+  int32_t* tab = A.after + SL * A.after_cap;
+  int S = suf - cnt;
+  for (int t = thi - 1; t >= tlo; --t) {
+    if (t < A.after_cap) tab[t] = S;
+    S += 3 * stream_rows_at(t, G.Hl, G.Wl, O, K, G.kk);
+  }
+  if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(suf, A.rev_cap);
+}
+
+constexpr int SCATTER_PX = 16384;  // pixels of a lane per k_rans_scatter workgroup
+
+// Workgroup (lane, chunk) reads a chunk of the lane's symbols in pixel order
+// (coalesced) and puts each at its place in its stream's coding order
+// (coding_slot plus the stream's symbols of later steps); raster order
+// reverses the raster index. The writes of a workgroup stay within its
+// lane's K streams.
+template <int O, int K>
+__global__ void __launch_bounds__(256) k_rans_scatter(RansEncArgs A) {
+  const int64_t L = blockIdx.x;
+  const StreamGeom G = stream_geom(A, L * K);
+  const int64_t npx = (int64_t)G.Hl * G.Wl;
+  const int64_t q0 = (int64_t)blockIdx.y * SCATTER_PX;
+  if (q0 >= npx) return;
+  const int64_t q1 = min<int64_t>(npx, q0 + SCATTER_PX);
+  const uint32_t* sym = A.sym + G.D.px_base * 3;
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+    const int i = (int)(q / G.Wl), j = (int)(q - (int64_t)i * G.Wl);
+    const uint32_t* sp = sym + ((int64_t)(G.y0 + i) * G.D.W + (G.x0 + j)) * 3;
+    const uint32_t v[3] = {sp[0], sp[1], sp[2]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int64_t SL = L, p;
+      if (A.order == 0) {
+        p = 3 * npx - 1 - (3 * q + c);
+      } else {
+        int kk, t, off;
+        coding_slot(i, j, c, G.Hl, G.Wl, O, K, kk, t, off);
+        SL = L * K + kk;
+        p = (int64_t)A.after[SL * A.after_cap + t] + off;
+      }
+      if (p >= 0 && p < A.rev_cap) A.rev[SL * A.rev_cap + p] = v[c];
+    }
+  }
 }
 
 // rANS-encodes n symbols (start | freq << 16) into state x, bytes written
@@ -1143,9 +1139,10 @@ hipError_t launch_sample(int h, int C, const DecArgs& a, int grid, int waves, hi
 }
 
 template <int O, int K>
-static void launch_gather(const RansEncArgs& a, hipStream_t s) {
-  const int64_t grid = (a.n_lanes * K * GATHER_SEGS + 63) / 64;
-  hipLaunchKernelGGL((k_rans_gather<O, K>), dim3((unsigned)grid), dim3(64), 0, s, a);
+static void launch_layout(const RansEncArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_rans_counts<O, K>), dim3((unsigned)(a.n_lanes * K)), dim3(64), 0, s, a);
+  const unsigned chunks = (unsigned)((a.max_lane_px + SCATTER_PX - 1) / SCATTER_PX);
+  hipLaunchKernelGGL((k_rans_scatter<O, K>), dim3((unsigned)a.n_lanes, chunks > 0 ? chunks : 1u), dim3(256), 0, s, a);
 }
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
@@ -1154,15 +1151,15 @@ hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const int sel = 3 * (a.h - 1) + (a.K == 1 ? 0 : a.K == 2 ? 1 : 2);
   switch (sel) {
-    case 0: launch_gather<2, 1>(a, s); break;
-    case 1: launch_gather<2, 2>(a, s); break;
-    case 2: launch_gather<2, 4>(a, s); break;
-    case 3: launch_gather<3, 1>(a, s); break;
-    case 4: launch_gather<3, 2>(a, s); break;
-    case 5: launch_gather<3, 4>(a, s); break;
-    case 6: launch_gather<4, 1>(a, s); break;
-    case 7: launch_gather<4, 2>(a, s); break;
-    default: launch_gather<4, 4>(a, s); break;
+    case 0: launch_layout<2, 1>(a, s); break;
+    case 1: launch_layout<2, 2>(a, s); break;
+    case 2: launch_layout<2, 4>(a, s); break;
+    case 3: launch_layout<3, 1>(a, s); break;
+    case 4: launch_layout<3, 2>(a, s); break;
+    case 5: launch_layout<3, 4>(a, s); break;
+    case 6: launch_layout<4, 1>(a, s); break;
+    case 7: launch_layout<4, 2>(a, s); break;
+    default: launch_layout<4, 4>(a, s); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

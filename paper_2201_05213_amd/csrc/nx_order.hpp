@@ -26,6 +26,27 @@ NXHD int stream_rows_at(int t, int Hl, int Wl, int o, int K, int kk) {
   return full * (16 / K) + (rem > kk ? (rem - kk + K - 1) / K : 0);
 }
 
+// The place of symbol (row i, column j, channel c) of an Hl x Wl lane in its
+// stream's coding order (the reverse decode order below), wavefront order:
+// its stream kk, its step t = j + o i, and its offset among the stream's
+// symbols of step t. The stream's symbols of later steps come first (their
+// count is added by the caller); within step t, those of the groups above
+// (visited first), then of the channels after c (B, G, R), then the
+// stream's rows above row i in the group (rows descending).
+NXHD void coding_slot(int i, int j, int c, int Hl, int Wl, int o, int K, int& kk, int& t, int& off) {
+  t = j + o * i;
+  int ilo, ihi;
+  step_rows(t, Hl, Wl, o, ilo, ihi);
+  const int n = ihi - ilo + 1, nfull = n / 16, rem = n - 16 * nfull;
+  const int g = (i - ilo) / 16, ts = ilo + 16 * g, r = i - ts;
+  kk = r % K;
+  const int len_g = nx_min(16, ihi - ts + 1);
+  const int rows_g = (len_g - kk + K - 1) / K;
+  const int rows_part = rem > kk ? (rem - kk + K - 1) / K : 0;
+  const int above = g < nfull ? (nfull - 1 - g) * (16 / K) + rows_part : 0;
+  off = 3 * above + (2 - c) * rows_g + (rows_g - 1 - (r - kk) / K);
+}
+
 // Symbols of a lane in decode order:
 //   wavefront: steps t ascending; within a step the active rows are cut into
 //   groups of 16 consecutive rows; per group channels R, G, B; per channel
@@ -37,7 +58,6 @@ NXHD int stream_rows_at(int t, int Hl, int Wl, int o, int K, int kk) {
 struct RevOrder {
   int Hl, Wl, o, raster, K, kk;
   int t, ilo, ihi, ts, te, c, i;
-  int tstop;  // the walk ends below this step
   bool done;
 
   // highest row of stream kk in rows [ts, te], or ts - 1 if it has none
@@ -51,7 +71,7 @@ struct RevOrder {
     for (;;) {
       step_rows(t, Hl, Wl, o, ilo, ihi);
       if (ilo <= ihi) break;
-      if (--t < tstop) { done = true; return; }
+      if (--t < 0) { done = true; return; }
     }
     ts = ilo + ((ihi - ilo) / 16) * 16;
     te = nx_min(ts + 15, ihi);
@@ -64,22 +84,14 @@ struct RevOrder {
       if (--c >= 0) { i = top_row(); continue; }
       ts -= 16;
       if (ts >= ilo) { te = ts + 15; c = 2; i = top_row(); continue; }
-      if (--t < tstop) { done = true; return; }
+      if (--t < 0) { done = true; return; }
       enter_step();
     }
   }
   NXHD void init(int Hl_, int Wl_, int o_, int raster_, int K_, int kk_) {
-    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; K = K_; kk = kk_; done = false; tstop = 0;
+    Hl = Hl_; Wl = Wl_; o = o_; raster = raster_; K = K_; kk = kk_; done = false;
     if (raster) { i = Hl - 1; j = Wl - 1; c = 2; return; }
     t = Wl + o * (Hl - 1) - 1;
-    enter_step();
-    settle();
-  }
-  // the wavefront walk over steps t_hi - 1 down to t_lo only (t_lo <= t_hi)
-  NXHD void init_steps(int Hl_, int Wl_, int o_, int K_, int kk_, int t_lo, int t_hi) {
-    Hl = Hl_; Wl = Wl_; o = o_; raster = 0; K = K_; kk = kk_; done = false; tstop = t_lo;
-    t = t_hi - 1;
-    if (t < tstop) { done = true; return; }
     enter_step();
     settle();
   }

@@ -115,7 +115,7 @@ def test_encoder_walk_reverses_decoder_order(tmp_path):
     assert " 0 bad" in r.stdout
 
 
-SEG_DRIVER = r"""
+SLOT_DRIVER = r"""
 #include <cstdio>
 #include <vector>
 #include <tuple>
@@ -123,57 +123,54 @@ SEG_DRIVER = r"""
 using namespace nx;
 typedef std::tuple<int, int, int> Sym;
 
-static std::vector<Sym> walk(RevOrder it) {
-  std::vector<Sym> v;
-  while (!it.done) { v.push_back(Sym(it.i, it.col(), it.c)); it.advance(); }
-  return v;
-}
-
 int main() {
   int cases = 0, bad = 0;
   for (int h = 1; h <= 3; ++h)
     for (int K : {1, 2, 4})
       for (int Hl = 1; Hl <= 90; Hl += (Hl < 6 ? 1 : 13))
-        for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13))
+        for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13)) {
+          ++cases;
+          const int o = h + 1, T = Wl + o * (Hl - 1);
+          // the encoder's walk of every stream, and each stream's symbols after each step
+          std::vector<std::vector<Sym>> walk(K);
+          std::vector<std::vector<long>> after(K, std::vector<long>(T, 0));
           for (int kk = 0; kk < K; ++kk) {
-            ++cases;
-            const int o = h + 1, T = Wl + o * (Hl - 1);
-            RevOrder full;
-            full.init(Hl, Wl, o, 0, K, kk);
-            const std::vector<Sym> ref = walk(full);
-            long total = 0;
-            for (int t = 0; t < T; ++t) total += 3 * stream_rows_at(t, Hl, Wl, o, K, kk);
-            if (total != (long)ref.size()) { ++bad; if (bad < 5) printf("count h%d K%d %dx%d kk%d: %ld vs %zu\n", h, K, Hl, Wl, kk, total, ref.size()); }
-            for (int S : {1, 3, 8, 32}) {
-              std::vector<Sym> cat;
-              for (int seg = S - 1; seg >= 0; --seg) {
-                const int lo = (int)((long)T * seg / S), hi = (int)((long)T * (seg + 1) / S);
-                long pos = 0;
-                for (int t = hi; t < T; ++t) pos += 3 * stream_rows_at(t, Hl, Wl, o, K, kk);
-                if (pos != (long)cat.size()) { ++bad; if (bad < 5) printf("pos h%d K%d %dx%d kk%d S%d seg%d\n", h, K, Hl, Wl, kk, S, seg); }
-                RevOrder it;
-                it.init_steps(Hl, Wl, o, K, kk, lo, hi);
-                const std::vector<Sym> part = walk(it);
-                cat.insert(cat.end(), part.begin(), part.end());
-              }
-              if (cat != ref) { ++bad; if (bad < 5) printf("walk h%d K%d %dx%d kk%d S%d\n", h, K, Hl, Wl, kk, S); }
-            }
+            RevOrder it;
+            it.init(Hl, Wl, o, 0, K, kk);
+            while (!it.done) { walk[kk].push_back(Sym(it.i, it.col(), it.c)); it.advance(); }
+            long S = 0;
+            for (int t = T - 1; t >= 0; --t) { after[kk][t] = S; S += 3 * stream_rows_at(t, Hl, Wl, o, K, kk); }
+            if (S != (long)walk[kk].size()) { ++bad; if (bad < 5) printf("length h%d K%d %dx%d kk%d\n", h, K, Hl, Wl, kk); }
           }
+          // every symbol's place from coding_slot is its index in its stream's walk
+          for (int i = 0; i < Hl; ++i)
+            for (int j = 0; j < Wl; ++j)
+              for (int c = 0; c < 3; ++c) {
+                int kk, t, off;
+                coding_slot(i, j, c, Hl, Wl, o, K, kk, t, off);
+                const long p = after[kk][t] + off;
+                if (kk < 0 || kk >= K || p < 0 || p >= (long)walk[kk].size() || walk[kk][p] != Sym(i, j, c)) {
+                  ++bad;
+                  if (bad < 5) printf("slot h%d K%d %dx%d (%d,%d,%d)\n", h, K, Hl, Wl, i, j, c);
+                }
+              }
+        }
   printf("%d cases, %d bad\n", cases, bad);
   return bad != 0;
 }
 """
 
 
-def test_segmented_walks_and_step_counts(tmp_path):
-    """The encoder's gather splits each stream's reverse walk into step
-    ranges: walks over consecutive ranges (highest first) concatenate to the
-    full walk, and each range starts at the position given by the per-step
-    stream counts (stream_rows_at) of the steps after it, whose total is the
-    stream's length."""
-    src = tmp_path / "seg.cpp"
-    exe = tmp_path / "seg"
-    src.write_text(SEG_DRIVER)
+def test_coding_slots_match_the_walk(tmp_path):
+    """The encoder lays each stream's symbols out in coding order from pixel
+    order: every symbol's place, coding_slot's offset within its step plus
+    the stream's symbols of later steps (from stream_rows_at), is its index
+    in the stream's reverse walk (RevOrder), and the per-step counts add up
+    to each stream's length; for lanes narrower than h + 1 columns, single
+    rows and columns, and ragged group sizes."""
+    src = tmp_path / "slot.cpp"
+    exe = tmp_path / "slot"
+    src.write_text(SLOT_DRIVER)
     cmd = ["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I", "/opt/rocm/include",
            str(src), "-o", str(exe)]
     r = subprocess.run(cmd, capture_output=True, text=True)
