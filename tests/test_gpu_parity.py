@@ -467,3 +467,23 @@ def test_balanced_patch_launch_shape(models, nx):
         assert plan.waves <= 8 and plan.grid <= cus
         assert plan.n_lanes <= plan.grid * plan.waves  # every lane in flight at once
         del ws
+
+
+@pytest.mark.parametrize("order,K", [(0, 1), (1, 1), (1, 2), (1, 4), (2, 4)])
+def test_whole_image_lanes_above_one_scatter_chunk(models, nx, order, K):
+    """Whole-image lanes larger than the 16,384 pixels one encoder scatter
+    workgroup lays out (160x130 and 150x140, with a small image in the same
+    batch): exact round trips in every order and stream count, the decoder's
+    symbols bitwise the encoder's."""
+    say(f"[gpu] whole-image lanes over one scatter chunk, order {order}, K={K}")
+    m, _, _ = models["A"]
+    shapes = [(160, 130), (40, 30), (150, 140)]
+    imgs = [synth.smooth_field_image(2.0, 3, 2, H, W, 900 + k) for k, (H, W) in enumerate(shapes)]
+    ts = [cuda(i) for i in imgs]
+    data, offs = m.encode(ts, order=order, interleave=K)
+    out, st, dump = m.decode(data, offs, shapes, order=order, trace=True, interleave=K)
+    assert int(st.abs().sum()) == 0
+    for a, b in zip(out, ts):
+        assert torch.equal(a, b)
+    sym, _ = m.debug_symbols(ts)
+    assert torch.equal(sym, dump)
