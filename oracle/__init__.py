@@ -57,6 +57,10 @@ def lib():
         L.ox_rans_encode.argtypes = [P, P, L64, P, S]
         L.ox_rans_decode.restype = L64
         L.ox_rans_decode.argtypes = [P, L64, P, S, P]
+        L.ox_spread_select.restype = ctypes.c_uint32
+        L.ox_spread_select.argtypes = [ctypes.c_uint32] * 3
+        L.ox_spread_rank.restype = ctypes.c_uint32
+        L.ox_spread_rank.argtypes = [ctypes.c_uint32] * 3
         L.ox_encode_offset.restype = L64
         L.ox_encode_offset.argtypes = [P, P, I, I, I, I, I, P, S]
         L.ox_decode_offset.restype = I
@@ -288,13 +292,24 @@ def rans_encode(start, freq) -> bytes:
     return out[:n].tobytes()
 
 
+def spread_select(x: int, start: int, freq: int) -> int:
+    """The x-th (from 0) slot y in [0, 2^16) whose 16-bit reversal lies in
+    [start, start + freq): where the coder puts a push from a state x < freq."""
+    return int(lib().ox_spread_select(x, start, freq))
+
+
+def spread_rank(y: int, start: int, freq: int) -> int:
+    """Number of spread slots of (start, freq) below y."""
+    return int(lib().ox_spread_rank(y, start, freq))
+
+
 def rans_decode(cdfs: np.ndarray, data: bytes):
     """cdfs: (N, 257) int32 rows; returns (symbols, ok)."""
     c = np.ascontiguousarray(cdfs, dtype=np.int32)
     N = c.shape[0]
-    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    buf = np.frombuffer(data, dtype=np.uint8).copy() if len(data) else np.zeros(1, dtype=np.uint8)
     sym = np.zeros(N, dtype=np.int32)
-    rc = lib().ox_rans_decode(_ptr(c), N, _ptr(buf), buf.size, _ptr(sym))
+    rc = lib().ox_rans_decode(_ptr(c), N, _ptr(buf), len(data), _ptr(sym))
     return sym, rc == 0
 
 

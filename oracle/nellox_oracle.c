@@ -21,7 +21,9 @@
  *     by the earlier channels;
  *   - 16-bit quantised CDFs: cdf_k = k + floor(clamp(F(B_k),0,1) * 65280);
  *   - a byte-renormalising rANS coder (stream coding, Sec. 2, Eq. (2) text),
- *     32-bit state, L = 2^23, precision 2^16, start state 1;
+ *     32-bit state, L = 2^23, precision 2^16, start state 1, states below
+ *     a symbol's frequency coded through its bit-reversal-spread slots, the
+ *     final state flushed as its significant bytes;
  *   - raster order (the sequential decoder of Sec. 2) and the topological
  *     (wavefront) order of Sec. 3 / Fig. 3: pixel (i,j) at step j + (h+1) i;
  *   - the patch scheme: an image is cut into patch_h x patch_w tiles anchored
@@ -285,8 +287,28 @@ static double ox_posterior(double *logw, const double *mu, const double *invs, i
 }
 
 /* ---------------------------------------------------------------- rANS */
-/* Byte-wise rANS (Duda 2013): state x in [L, 2^31) between symbols once the
- * start-up phase is over; encoder starts at x = 1; four flush bytes. */
+/* Byte-wise rANS (Duda 2013) with precision M = 2^16, L = 2^23, a 32-bit
+ * state, and no wasted start-up or flush bits:
+ *   - the encoder starts at x = 1 and the decoder must end there: a damaged
+ *     stream that runs out of bytes drains to 0, which a spread pop never
+ *     leaves (the cost of this check is about one bit);
+ *   - a push of symbol (s, f) from a state x >= f is the usual
+ *     x <- floor(x / f) M + (x mod f) + s, after emitting low bytes while
+ *     x >= 2^15 f;
+ *   - a push from a state x < f (only ever at the start of a stream) uses
+ *     the symbol's spread slots instead of its range [s, s + f): x <- the
+ *     x-th (from 0) of the slots y in [0, M) whose 16-bit reversal lies in
+ *     [s, s + f). Reversal deals f consecutive values out over [0, M) about
+ *     M / f apart (every block of 2^(16-p) slots, 2^p <= f, holds one), so
+ *     the state grows by about M / f, as it does once it is large; the usual
+ *     rule would jump to s + x. Both rules are bijections, the first onto the
+ *     states >= M, the second onto [0, M), so the decoder tells them apart by
+ *     x < M;
+ *   - the final state is flushed as its significant bytes only, most
+ *     significant first; the decoder starts from x = 0 and reads bytes
+ *     while x < L, as in any renormalisation.
+ * A stream therefore costs its ideal length plus about the rounding of its
+ * last byte. */
 
 typedef struct {
   uint8_t *tmp; size_t n, cap; /* bytes in emission order */
@@ -303,49 +325,106 @@ static int ox_push(ox_bytes *b, uint8_t v) {
   return OX_OK;
 }
 
+/* 16-bit bit reversal, from a table filled bit by bit on first use */
+static uint16_t ox_rev_table[OX_TOTAL];
+static int ox_rev_ready = 0;
+
+static uint32_t ox_rev16(uint32_t v) {
+  if (!ox_rev_ready) {
+    for (uint32_t u = 0; u < OX_TOTAL; ++u) {
+      uint32_t r = 0;
+      for (int b = 0; b < 16; ++b)
+        if (u & (1u << b)) r |= 1u << (15 - b);
+      ox_rev_table[u] = (uint16_t)r;
+    }
+    ox_rev_ready = 1;
+  }
+  return ox_rev_table[v & 0xffffu];
+}
+
+static int ox_is_spread_slot(uint32_t y, uint32_t s, uint32_t f) {
+  uint32_t v = ox_rev16(y);
+  return v >= s && v < s + f;
+}
+
+/* The x-th spread slot of symbol (s, f), x < f: a plain scan. */
+uint32_t ox_spread_select(uint32_t x, uint32_t s, uint32_t f) {
+  uint32_t n = 0;
+  for (uint32_t y = 0; y < OX_TOTAL; ++y)
+    if (ox_is_spread_slot(y, s, f)) {
+      if (n == x) return y;
+      ++n;
+    }
+  return OX_TOTAL; /* x >= f */
+}
+
+/* Index of slot y among the spread slots of (s, f): slots below y. */
+uint32_t ox_spread_rank(uint32_t y, uint32_t s, uint32_t f) {
+  uint32_t n = 0;
+  for (uint32_t u = 0; u < y; ++u) n += (uint32_t)ox_is_spread_slot(u, s, f);
+  return n;
+}
+
 /* Encode symbols (start[n], freq[n]) given in decode order; writes the
- * stream (4 state bytes LE, then renormalisation bytes in read order) into
- * out. Returns the byte count or a negative error. */
+ * stream (final state's significant bytes, most significant first, then the
+ * renormalisation bytes in read order) into out. Returns the byte count or
+ * a negative error. */
 long ox_rans_encode(const uint32_t *start, const uint32_t *freq, long N, uint8_t *out, size_t cap) {
   ox_bytes b = {0, 0, 0};
   uint32_t x = 1;
   for (long n = N - 1; n >= 0; --n) {
     uint32_t f = freq[n], s = start[n];
     if (f == 0 || f > OX_TOTAL || s + f > OX_TOTAL) { free(b.tmp); return OX_E_ARG; }
+    if (x < f) {
+      x = ox_spread_select(x, s, f);
+      continue;
+    }
     uint64_t xmax = (uint64_t)(OX_RANS_L >> 16) * 256u * f;
     while ((uint64_t)x >= xmax) { ox_push(&b, (uint8_t)(x & 255u)); x >>= 8; }
     x = ((x / f) << 16) + (x % f) + s;
   }
-  size_t total = 4 + b.n;
+  size_t nstate = 0;
+  for (uint32_t v = x; v; v >>= 8) ++nstate;
+  size_t total = nstate + b.n;
   if (total > cap) { free(b.tmp); return OX_E_CAP; }
-  for (int k = 0; k < 4; ++k) out[k] = (uint8_t)(x >> (8 * k));
-  for (size_t k = 0; k < b.n; ++k) out[4 + k] = b.tmp[b.n - 1 - k];
+  for (size_t k = 0; k < nstate; ++k) out[k] = (uint8_t)(x >> (8 * (nstate - 1 - k)));
+  for (size_t k = 0; k < b.n; ++k) out[nstate + k] = b.tmp[b.n - 1 - k];
   free(b.tmp);
   return (long)total;
 }
 
 typedef struct {
-  uint32_t x; const uint8_t *buf; size_t len, pos; int bad;
+  uint32_t x; const uint8_t *buf; size_t len, pos;
 } ox_rdec;
 
-static void ox_rdec_init(ox_rdec *d, const uint8_t *buf, size_t len) {
-  d->buf = buf; d->len = len; d->bad = 0;
-  if (len < 4) { d->bad = 1; d->x = 0; d->pos = len; return; }
-  d->x = rd32(buf); d->pos = 4;
-}
-
-static uint32_t ox_rdec_slot(const ox_rdec *d) { return d->x & 0xffffu; }
-
-static void ox_rdec_advance(ox_rdec *d, uint32_t s, uint32_t f) {
-  d->x = f * (d->x >> 16) + (d->x & 0xffffu) - s;
+static void ox_rdec_fill(ox_rdec *d) {
   while (d->x < OX_RANS_L && d->pos < d->len) d->x = (d->x << 8) | d->buf[d->pos++];
 }
+
+static void ox_rdec_init(ox_rdec *d, const uint8_t *buf, size_t len) {
+  d->buf = buf; d->len = len; d->pos = 0; d->x = 0;
+  ox_rdec_fill(d);
+}
+
+/* The value the symbol is searched with: the slot x mod M, or for a state
+ * below M (a spread push) the reversal of the slot. */
+static uint32_t ox_rdec_slot(const ox_rdec *d) {
+  return d->x < OX_TOTAL ? ox_rev16(d->x) : (d->x & 0xffffu);
+}
+
+static void ox_rdec_advance(ox_rdec *d, uint32_t s, uint32_t f) {
+  if (d->x < OX_TOTAL) d->x = ox_spread_rank(d->x, s, f);
+  else d->x = f * (d->x >> 16) + (d->x & 0xffffu) - s;
+  ox_rdec_fill(d);
+}
+
+/* a stream ends in the encoder's start state with every byte read */
+static int ox_rdec_clean(const ox_rdec *d) { return d->x == 1u && d->pos == d->len; }
 
 /* Decode N symbols, each with its own CDF row cdfs[n*257..]. */
 long ox_rans_decode(const int32_t *cdfs, long N, const uint8_t *in, size_t len, int32_t *sym) {
   ox_rdec d;
   ox_rdec_init(&d, in, len);
-  if (d.bad) return OX_E_CORRUPT;
   for (long n = 0; n < N; ++n) {
     const int32_t *c = cdfs + 257 * n;
     uint32_t slot = ox_rdec_slot(&d);
@@ -354,7 +433,7 @@ long ox_rans_decode(const int32_t *cdfs, long N, const uint8_t *in, size_t len, 
     sym[n] = k;
     ox_rdec_advance(&d, (uint32_t)c[k], (uint32_t)(c[k + 1] - c[k]));
   }
-  return (d.x == 1u && d.pos == d.len) ? OX_OK : OX_E_CORRUPT;
+  return ox_rdec_clean(&d) ? OX_OK : OX_E_CORRUPT;
 }
 
 /* ---------------------------------------------------------------- schedule */
@@ -587,7 +666,7 @@ static int ox_decode_lane(const ox_model *m, const uint8_t *in, size_t len, ox_r
   long N = ox_symbol_order(r.h, r.w, offset, seq);
   ox_rdec d;
   ox_rdec_init(&d, in, len);
-  int rc = d.bad ? OX_E_CORRUPT : OX_OK;
+  int rc = OX_OK;
   int32_t cdf[257];
   double mu[OX_NMIX];
   for (long k = 0; k < N && !rc; ++k) {
@@ -604,7 +683,7 @@ static int ox_decode_lane(const ox_model *m, const uint8_t *in, size_t len, ox_r
     cv[pi * 3 + c] = ox_normalise(v);
     img[(((long)(r.y0 + y)) * W_img + r.x0 + x) * 3 + c] = (uint8_t)v;
   }
-  if (!rc && !(d.x == 1u && d.pos == d.len)) rc = OX_E_CORRUPT;
+  if (!rc && !ox_rdec_clean(&d)) rc = OX_E_CORRUPT;
   free(cv); free(pxs); free(seq);
   return rc;
 }
@@ -816,7 +895,7 @@ static int ox_decode_lane_shear(const ox_model *m, const double *Kp, const uint8
   long N = ox_symbol_order(H, W, o, seq);
   ox_rdec d;
   ox_rdec_init(&d, in, len);
-  int rc = d.bad ? OX_E_CORRUPT : OX_OK;
+  int rc = OX_OK;
   int32_t cdf[257];
   double mu[OX_NMIX], th[OX_NOUT];
   for (long k = 0; k < N && !rc; ++k) {
@@ -839,7 +918,7 @@ static int ox_decode_lane_shear(const ox_model *m, const double *Kp, const uint8
     S[((long)i * L + t) * 3 + c] = ox_normalise(v);
     Sb[((long)i * L + t) * 3 + c] = (double)v;
   }
-  if (!rc && !(d.x == 1u && d.pos == d.len)) rc = OX_E_CORRUPT;
+  if (!rc && !ox_rdec_clean(&d)) rc = OX_E_CORRUPT;
   if (!rc) {
     ox_unshear(Sb, H, W, 3, o, out);
     for (int i = 0; i < H; ++i)
