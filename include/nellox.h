@@ -15,8 +15,11 @@
  *   Probabilities are quantised to 16-bit CDFs
  *       cdf_k = k + floor(clamp(F(B_k), 0, 1) * 65280),  B_k = (2k - 256)/255,
  *   so every symbol has frequency >= 1 and the total is 2^16, and coded with
- *   byte-renormalising rANS (32-bit state, L = 2^23, start state 1), one
- *   stream per lane or K = 2, 4 interleaved streams per lane (opts.interleave):
+ *   byte-renormalising rANS (32-bit state, L = 2^23, start state 1; a push
+ *   from a state below the symbol's frequency f takes the x-th of the slots
+ *   whose 16-bit reversal lies in the symbol's range, so it grows the state
+ *   by about 2^16 / f; the final state is flushed as its significant bytes),
+ *   one stream per lane or K = 2, 4 interleaved streams per lane (opts.interleave):
  *   in a wavefront step, row i - i_first goes to stream (i - i_first) mod K.
  *   Decoding order (nellox_opts.order):
  *     0 raster: one pixel after the other (the sequential decoder of Sec. 2);
@@ -75,7 +78,8 @@ typedef struct {
   int32_t interleave; /* rANS states per lane: 0 or 1 = one; 2 or 4 (wavefront order
                          only): the rows of every wavefront step are dealt to the
                          states in turn, so a decoder can search that many symbols
-                         at once; each extra state costs one stream flush */
+                         at once; each extra state costs one stream's start and
+                         flush, a few bits */
 } nellox_opts;
 
 typedef struct {
@@ -104,8 +108,19 @@ nellox_status nellox_model_info(const nellox_model* m, int32_t dims[4], uint64_t
 size_t nellox_encode_bound(int32_t H, int32_t W, const nellox_opts* opts);
 
 /* Device workspace bytes that encode, decode, nll and the debug calls need
- * for this batch (the maximum over them). */
+ * for this batch (the maximum over them: the encoder's). With K streams per
+ * lane about (28 + 6 K) B per pixel plus 16 K (patch_w + 4 patch_h) B per
+ * lane: it grows with the sum of the lanes; 0 if the arguments are invalid. */
 size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* opts);
+
+/* Device workspace bytes of every call but nellox_encode for this batch:
+ * nellox_decode, nellox_decode_trace, nellox_decode_prepare / _run,
+ * nellox_sample, nellox_nll, nellox_debug_symbols and nellox_debug_cdf (image
+ * descriptors, the lane queue, the sheared layout's context windows, 4 B of
+ * per-pixel bits and the per-image partial sums); at most
+ * nellox_workspace_bytes. 0 if the arguments are invalid. */
+size_t nellox_decode_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs,
+                                     const nellox_opts* opts);
 
 /* Encode n images (Sec. 2 stream coding; every pixel's CDF is computed in one
  * full-image pass, then each lane is rANS-coded in reverse decode order).
@@ -121,7 +136,8 @@ nellox_status nellox_encode(const nellox_model* m, int32_t n, const nellox_image
 nellox_status nellox_peek(const uint8_t* container, size_t len, int32_t* H, int32_t* W, nellox_opts* opts);
 
 /* Decode n containers (device buffer `in`, image k at in[in_offsets[k] ..
- * in_offsets[k+1]), in_offsets on the device) into the preallocated images
+ * in_offsets[k+1]), exactly the container's bytes, in_offsets on the
+ * device) into the preallocated images
  * out[k] (H, W from nellox_peek). opts must match the containers (order and
  * patch shape). status: n device int32, set to NELLOX_OK or a data error per
  * image. Wavefront order runs Algorithm 1 of the paper per lane, with all
@@ -227,11 +243,12 @@ int64_t nellox_param_count(const int32_t dims[4]);
 size_t nellox_train_workspace_bytes(const int32_t dims[4], int32_t n, int32_t H, int32_t W);
 
 /* Forward: bits_per_img[k] (device, n doubles) = -log2 p(image k), the joint
- * mixture likelihood of every pixel summed in FP64. Saves in ws what
- * nellox_nll_bwd needs. */
+ * mixture likelihood of every pixel summed in FP64; bits_per_px (device,
+ * n*H*W floats, nullable) receives each pixel's -log2 p in FP32, images and
+ * rows in order. Saves in ws what nellox_nll_bwd needs. */
 nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n,
-                                   int32_t H, int32_t W, double* bits_per_img, void* ws, size_t ws_bytes,
-                                   void* stream);
+                                   int32_t H, int32_t W, double* bits_per_img, float* bits_per_px, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Backward: grad_params (device, overwritten) = sum_k grad_bits[k] *
  * d bits_k / d params, grad_bits: device, n floats. ws must still hold the

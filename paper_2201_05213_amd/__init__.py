@@ -72,8 +72,11 @@ class Model:
             pass
 
     # ------------------------------------------------------------------ helpers
-    def workspace(self, imgs_arr, n, opts) -> torch.Tensor:
-        nb = load().nellox_workspace_bytes(self._h, n, imgs_arr, ctypes.byref(opts))
+    def workspace(self, imgs_arr, n, opts, encode: bool = True) -> torch.Tensor:
+        """Workspace for this batch: of every call (encode=True), or of every
+        call but encode (decoding, sampling, NLL, debug)."""
+        fn = load().nellox_workspace_bytes if encode else load().nellox_decode_workspace_bytes
+        nb = fn(self._h, n, imgs_arr, ctypes.byref(opts))
         if nb == 0:
             raise NelloxError(1, "nellox_workspace_bytes")
         return torch.empty(nb, dtype=torch.uint8, device=self.device)
@@ -117,7 +120,7 @@ class Model:
         arr = _images(imgs)
         status = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         if ws is None:
-            ws = self.workspace(arr, n, o)
+            ws = self.workspace(arr, n, o, encode=False)
         data = data.contiguous()
         offsets = offsets.to(device=self.device, dtype=torch.int64).contiguous()
         if trace:
@@ -149,7 +152,7 @@ class Model:
         o = _opts(order, patch, interleave)
         arr = _images(out)
         if ws is None:
-            ws = self.workspace(arr, n, o)
+            ws = self.workspace(arr, n, o, encode=False)
         plan = NelloxDecodePlan()
         check(L.nellox_decode_prepare(self._h, n, arr, ctypes.byref(o), ws.data_ptr(), ws.numel(), ctypes.byref(plan),
                                       _stream(self.device)), "nellox_decode_prepare")
@@ -175,7 +178,7 @@ class Model:
         arr = _images(imgs)
         sd = (ctypes.c_uint64 * max(n, 1))(*[int(v) & 0xFFFFFFFFFFFFFFFF for v in seeds])
         if ws is None:
-            ws = self.workspace(arr, n, o)
+            ws = self.workspace(arr, n, o, encode=False)
         check(L.nellox_sample(self._h, n, sd, ctypes.byref(o), arr, ws.data_ptr(), ws.numel(), _stream(self.device)),
               "nellox_sample")
         return imgs
@@ -186,7 +189,7 @@ class Model:
         n = len(imgs)
         o = _opts(WAVEFRONT, patch)
         arr = _images(imgs)
-        ws = self.workspace(arr, n, o)
+        ws = self.workspace(arr, n, o, encode=False)
         tot = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
         npx = sum(int(t.shape[0]) * int(t.shape[1]) for t in imgs)
         px = torch.empty(max(npx, 1), dtype=torch.float32, device=self.device) if per_pixel else None
@@ -201,7 +204,7 @@ class Model:
         n = len(imgs)
         o = _opts(WAVEFRONT, patch)
         arr = _images(imgs)
-        ws = self.workspace(arr, n, o)
+        ws = self.workspace(arr, n, o, encode=False)
         npx = sum(int(t.shape[0]) * int(t.shape[1]) for t in imgs)
         sym = torch.zeros(max(npx * 3, 1), dtype=torch.int32, device=self.device)
         ideal = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
@@ -214,7 +217,7 @@ class Model:
         L = load()
         o = _opts(WAVEFRONT, patch)
         arr = _images([img])
-        ws = self.workspace(arr, 1, o)
+        ws = self.workspace(arr, 1, o, encode=False)
         H, W = int(img.shape[0]), int(img.shape[1])
         cdf = torch.empty((H, W, 3, 257), dtype=torch.int32, device=self.device)
         check(L.nellox_debug_cdf(self._h, arr, ctypes.byref(o), cdf.data_ptr(), ws.data_ptr(), ws.numel(),

@@ -37,6 +37,7 @@ SIGNATURES = {
     "nellox_model_info": (_ST, [_P, _P, _P]),
     "nellox_encode_bound": (_SZ, [_I32, _I32, _P]),
     "nellox_workspace_bytes": (_SZ, [_P, _I32, _P, _P]),
+    "nellox_decode_workspace_bytes": (_SZ, [_P, _I32, _P, _P]),
     "nellox_encode": (_ST, [_P, _I32, _P, _P, _P, _SZ, _P, _P, _SZ, _P]),
     "nellox_peek": (_ST, [_P, _SZ, _P, _P, _P]),
     "nellox_decode": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -50,7 +51,7 @@ SIGNATURES = {
     "nellox_debug_check_monotone": (_ST, [_P, _P]),
     "nellox_param_count": (ctypes.c_int64, [_P]),
     "nellox_train_workspace_bytes": (_SZ, [_P, _I32, _I32, _I32]),
-    "nellox_nll_fwd_train": (_ST, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _SZ, _P]),
+    "nellox_nll_fwd_train": (_ST, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "nellox_nll_bwd": (_ST, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "nellox_last_error": (ctypes.c_char_p, []),
 }

@@ -103,8 +103,8 @@ struct Plan {
   int order = 0;   // 0 raster, 1 wavefront, 2 wavefront decoded in the sheared layout
   int ph_max = 0;  // tallest lane of the batch
   int64_t ring_waves = 0, ring_rows = 0;  // sheared context rings (set by plan_ring)
-  int64_t rev_cap = 0;    // words per rANS stream for the encoder's symbols in coding order
-  int64_t after_cap = 0;  // entries per stream of the encoder's per-step offsets
+  int64_t rev_words = 0;    // encoder: coding-order symbol words of all streams
+  int64_t after_words = 0;  // encoder: per-step offset entries of all streams
   int64_t max_lane_px = 0;
 };
 
@@ -147,18 +147,22 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     P.n_tiles += (int64_t)im.H * D.ntx;
     P.ph_max = std::max(P.ph_max, D.ph);
     P.slot_bytes += P.K * (6 * npx + 8 * nl);
-    // a stream holds at most ceil(n / K) + 1 rows of each step of n rows:
-    // 3 (ph pw / K + T) symbols, T = pw + (h + 1)(ph - 1) steps, h + 1 <= 4
-    const int64_t cap = 3 * (((int64_t)D.ph * D.pw + P.K - 1) / P.K + D.pw + 4 * ((int64_t)D.ph - 1));
-    P.rev_cap = std::max(P.rev_cap, (cap + 15) / 16 * 16);
-    P.after_cap = std::max(P.after_cap, (int64_t)D.pw + 4 * ((int64_t)D.ph - 1) + 1);
+    D.rev_base = P.rev_words;
+    D.after_base = P.after_words;
+    P.rev_words += nl * P.K * stream_rev_words(D.ph, D.pw, P.K);
+    P.after_words += nl * P.K * stream_after_entries(D.ph, D.pw);
     P.max_lane_px = std::max(P.max_lane_px, (int64_t)D.ph * D.pw);
   }
   return NELLOX_OK;
 }
 
+// Workspace segments: first those of decoding, sampling, the NLL and the
+// debug calls (descriptors, queue counter, sheared windows, per-pixel bits,
+// partial sums; `small` bytes), then the encoder's alone (per-image sizes,
+// stream lengths, symbols, stream slots, coding-order buffers).
 struct WsLayout {
-  int64_t desc, sym, slots, lane_len, lane_end, img_bytes, flags, bits, partials, ring, rev, after, total;
+  int64_t desc, flags, ring, bits, partials, small;
+  int64_t img_bytes, lane_len, lane_end, sym, slots, rev, after, total;
 };
 
 WsLayout ws_layout(const Plan& P, int n) {
@@ -167,15 +171,16 @@ WsLayout ws_layout(const Plan& P, int n) {
   W.desc = o; o = align256(o + (int64_t)sizeof(ImgDesc) * std::max(n, 1));
   W.flags = o; o = align256(o + 64);
   W.ring = o; o = align256(o + P.ring_waves * ring_wave_bytes(P.ring_rows));
+  W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
+  W.partials = o; o = align256(o + 8LL * REDUCE_PARTS * std::max(n, 1));
+  W.small = o;
   W.img_bytes = o; o = align256(o + 8LL * std::max(n, 1));
   W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
   W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
-  W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
-  W.partials = o; o = align256(o + 8LL * REDUCE_PARTS * std::max(n, 1));
   W.sym = o; o = align256(o + 12 * std::max<int64_t>(P.n_px, 1));
   W.slots = o; o = align256(o + std::max<int64_t>(P.slot_bytes, 1));
-  W.rev = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K * P.rev_cap, 1));
-  W.after = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K * P.after_cap, 1));
+  W.rev = o; o = align256(o + 4 * std::max<int64_t>(P.rev_words, 1));
+  W.after = o; o = align256(o + 4 * std::max<int64_t>(P.after_words, 1));
   W.total = o;
   return W;
 }
@@ -420,7 +425,7 @@ size_t nellox_encode_bound(int32_t H, int32_t W, const nellox_opts* o) {
   const int64_t K = (!o || o->interleave <= 1) ? 1 : o->interleave;
   if (!valid_interleave((int)K)) return 0;
   const int64_t nl = (int64_t)((H + ph - 1) / ph) * ((W + pw - 1) / pw);
-  // header, stream table, per stream 4 flush bytes, at most 2 bytes per symbol
+  // header, stream table, per stream at most 4 flush bytes, at most 2 bytes per symbol
   return (size_t)(HDR_BYTES + 4 * nl * K + 4 * nl * K + 6LL * H * W);
 }
 
@@ -430,6 +435,15 @@ size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_ima
   if (make_plan(n, imgs, o, P, false) != NELLOX_OK) return 0;
   plan_ring(m, P);
   return (size_t)ws_layout(P, n).total;
+}
+
+size_t nellox_decode_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs,
+                                     const nellox_opts* o) {
+  if (!m) return 0;
+  Plan P;
+  if (make_plan(n, imgs, o, P, false) != NELLOX_OK) return 0;
+  plan_ring(m, P);
+  return (size_t)ws_layout(P, n).small;
 }
 
 nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_image* imgs, const nellox_opts* o,
@@ -461,9 +475,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   r.slots = w8 + W.slots;
   r.lane_len = (uint32_t*)(w8 + W.lane_len);
   r.rev = (uint32_t*)(w8 + W.rev);
-  r.rev_cap = P.rev_cap;
   r.after = (int32_t*)(w8 + W.after);
-  r.after_cap = P.after_cap;
   r.max_lane_px = P.max_lane_px;
   hipError_t e = launch_rans_encode(r, s);
   if (e != hipSuccess) return hip_fail(e, "rANS encoder launch");
@@ -516,7 +528,7 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   plan_ring(m, P);
   if (n > 0 && !ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
-  if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && (st = upload_plan(m, P, (uint8_t*)ws, W, s))) return st;
   int grid = 0, waves = 0;
@@ -531,7 +543,7 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   plan->ring_rows = P.ring_rows;
   plan->n_lanes = P.n_lanes;
   plan->model_hash = m->hash;
-  plan->ws_bytes = W.total;
+  plan->ws_bytes = W.small;
   plan->desc_offset = W.desc;
   plan->counter_offset = W.flags + 4;
   hipError_t e = prepare_decode(m->h, m->Cp, P.K);
@@ -627,7 +639,7 @@ nellox_status nellox_sample(const nellox_model* mc, int32_t n, const uint64_t* s
   if (n == 0) return NELLOX_OK;
   if (!ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
-  if ((int64_t)ws_bytes < W.img_bytes) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
   for (int k = 0; k < n; ++k) P.d[k].seed = seeds[k];
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
@@ -666,7 +678,7 @@ nellox_status nellox_nll(const nellox_model* mc, int32_t n, const nellox_image* 
   if (st) return st;
   if (n > 0 && (!bits_total || !ws)) return fail(NELLOX_E_ARG, "null pointer argument");
   const WsLayout W = ws_layout(P, n);
-  if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
   if (n == 0) return NELLOX_OK;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
@@ -688,7 +700,7 @@ nellox_status nellox_debug_symbols(const nellox_model* mc, int32_t n, const nell
   if (st) return st;
   if (n > 0 && (!sym || !ws)) return fail(NELLOX_E_ARG, "null pointer argument");
   const WsLayout W = ws_layout(P, n);
-  if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
   if (n == 0) return NELLOX_OK;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
@@ -718,7 +730,7 @@ nellox_status nellox_debug_cdf(const nellox_model* mc, const nellox_image* img, 
   if (st) return st;
   if (!cdf || !ws) return fail(NELLOX_E_ARG, "null pointer argument");
   const WsLayout W = ws_layout(P, 1);
-  if ((int64_t)ws_bytes < W.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
   if ((st = upload_plan(m, P, w8, W, s))) return st;
@@ -737,8 +749,8 @@ size_t nellox_train_workspace_bytes(const int32_t dims[4], int32_t n, int32_t H,
 }
 
 nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n,
-                                   int32_t H, int32_t W, double* bits_per_img, void* ws, size_t ws_bytes,
-                                   void* stream) {
+                                   int32_t H, int32_t W, double* bits_per_img, float* bits_per_px, void* ws,
+                                   size_t ws_bytes, void* stream) {
   TrainPlan T;
   nellox_status st = train_plan(dims, n, H, W, T, true);
   if (st) return st;
@@ -754,6 +766,10 @@ nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], c
   if (e != hipSuccess) return hip_fail(e, "training forward launch");
   e = launch_bits_img(a.bits, T.n, (int64_t)T.H * T.W, bits_per_img, s);
   if (e != hipSuccess) return hip_fail(e, "bits reduction launch");
+  if (bits_per_px) {
+    e = hipMemcpyAsync(bits_per_px, a.bits, 4 * (size_t)T.npx, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "per-pixel bits copy");
+  }
   return NELLOX_OK;
 }
 

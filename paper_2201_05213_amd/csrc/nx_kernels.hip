@@ -165,11 +165,13 @@ __global__ void __launch_bounds__(NWAVES * 64) k_pass(PassArgs A) {
 // contiguously in coding order, reading the symbol buffer in pixel order;
 // k_rans_enc then reads them in order and codes.
 
-// lane geometry of stream SL = L K + kk
+// lane geometry of stream SL = L K + kk, and where its encoder scratch lies
 struct StreamGeom {
   ImgDesc D;
   int kk, q, y0, x0, Hl, Wl;
   int64_t lane_px_off;
+  int64_t rev_cap, rev_off;      // words of the stream's coding-order buffer, and its first
+  int64_t after_cap, after_off;  // entries of its per-step offsets, and its first
 };
 NXD StreamGeom stream_geom(const RansEncArgs& A, int64_t SL) {
   StreamGeom G;
@@ -178,6 +180,11 @@ NXD StreamGeom stream_geom(const RansEncArgs& A, int64_t SL) {
   const int n = find_img(A.desc, A.n_img, L, true);
   G.D = A.desc[n];
   G.q = (int)(L - G.D.lane_base);
+  const int64_t rel = SL - G.D.lane_base * A.K;  // the stream's index within its image
+  G.rev_cap = stream_rev_words(G.D.ph, G.D.pw, A.K);
+  G.after_cap = stream_after_entries(G.D.ph, G.D.pw);
+  G.rev_off = G.D.rev_base + rel * G.rev_cap;
+  G.after_off = G.D.after_base + rel * G.after_cap;
   const int ly = G.q / G.D.nlx, lx = G.q - ly * G.D.nlx;
   G.y0 = ly * G.D.ph;
   G.x0 = lx * G.D.pw;
@@ -199,7 +206,7 @@ __global__ void __launch_bounds__(64) k_rans_counts(RansEncArgs A) {
   const int lane = (int)threadIdx.x;
   const StreamGeom G = stream_geom(A, SL);
   if (A.order == 0) {
-    if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(3LL * G.Hl * G.Wl, A.rev_cap);
+    if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(3LL * G.Hl * G.Wl, G.rev_cap);
     return;
   }
   const int T = G.Wl + O * (G.Hl - 1);
@@ -212,13 +219,13 @@ __global__ void __launch_bounds__(64) k_rans_counts(RansEncArgs A) {
     const int v = __shfl_down(suf, d, 64);
     if (lane + d < 64) suf += v;
   }
-  int32_t* tab = A.after + SL * A.after_cap;
+  int32_t* tab = A.after + G.after_off;
   int S = suf - cnt;
   for (int t = thi - 1; t >= tlo; --t) {
-    if (t < A.after_cap) tab[t] = S;
+    if (t < G.after_cap) tab[t] = S;
     S += 3 * stream_rows_at(t, G.Hl, G.Wl, O, K, G.kk);
   }
-  if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(suf, A.rev_cap);
+  if (lane == 0) A.lane_len[SL] = (uint32_t)min<int64_t>(suf, G.rev_cap);
 }
 
 constexpr int SCATTER_PX = 16384;  // pixels of a lane per k_rans_scatter workgroup
@@ -243,30 +250,74 @@ __global__ void __launch_bounds__(256) k_rans_scatter(RansEncArgs A) {
     const uint32_t v[3] = {sp[0], sp[1], sp[2]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      int64_t SL = L, p;
+      int kk = 0;
+      int64_t p;
       if (A.order == 0) {
         p = 3 * npx - 1 - (3 * q + c);
       } else {
-        int kk, t, off;
+        int t, off;
         coding_slot(i, j, c, G.Hl, G.Wl, O, K, kk, t, off);
-        SL = L * K + kk;
-        p = (int64_t)A.after[SL * A.after_cap + t] + off;
+        p = (int64_t)A.after[G.after_off + kk * G.after_cap + t] + off;
       }
-      if (p >= 0 && p < A.rev_cap) A.rev[SL * A.rev_cap + p] = v[c];
+      if (p >= 0 && p < G.rev_cap) A.rev[G.rev_off + kk * G.rev_cap + p] = v[c];
     }
   }
+}
+
+// Spread slots. A push of symbol (s, f) from a state x < f (only near the
+// start of a stream) takes the x-th (from 0) slot y of [0, 2^16) whose 16-bit
+// reversal lies in [s, s + f): reversal deals the range out about 2^16 / f
+// apart, so the state grows by about the symbol's probability, where the
+// usual rule would jump to s + x. The decoder recognises such a state (it is
+// below 2^16), searches the symbol with the reversed slot and pops by the
+// rank of y among the symbol's slots. Both walk the reversal's 16 bits from
+// the lowest: the range values with low bits r (j of them) and bit j clear
+// number floor((s + f - 1 - r) / 2^(j+1)) - floor((s - 1 - r) / 2^(j+1))
+// (the floors are arithmetic shifts).
+NXD uint32_t rev16(uint32_t v) { return __builtin_bitreverse32(v) >> 16; }
+
+NXD int32_t spread_count(int32_t lo, int32_t hi, int32_t r, int sh) { return ((hi - r) >> sh) - ((lo - r) >> sh); }
+
+NXD uint32_t spread_select(uint32_t x, uint32_t s, uint32_t f) {
+  const int32_t lo = (int32_t)s - 1, hi = (int32_t)(s + f) - 1;
+  int32_t r = 0, left = (int32_t)x;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int32_t n0 = spread_count(lo, hi, r, j + 1);
+    const bool one = left >= n0;
+    left -= one ? n0 : 0;
+    r |= one ? (1 << j) : 0;
+  }
+  return rev16((uint32_t)r);
+}
+
+NXD uint32_t spread_rank(uint32_t y, uint32_t s, uint32_t f) {
+  const uint32_t v = rev16(y);
+  const int32_t lo = (int32_t)s - 1, hi = (int32_t)(s + f) - 1;
+  int32_t n = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int32_t r = (int32_t)(v & ((1u << j) - 1u));
+    n += ((v >> j) & 1u) ? spread_count(lo, hi, r, j + 1) : 0;
+  }
+  return (uint32_t)n;
 }
 
 // rANS-encodes n symbols (start | freq << 16) into state x, bytes written
 // backwards at out. x / f: a float quotient (relative error below 2^-21, so
 // within one of the true one, as x / f < 2^15 after renormalisation) fixed
 // by one step of the remainder; a state below 2^31 sheds at most two bytes.
+// A state below f takes the symbol's spread slot instead.
 template <int B>
 __device__ __forceinline__ void rans_put(uint32_t& x, uint8_t*& out, const uint32_t (&v)[B], int n) {
 #pragma unroll
   for (int k = 0; k < B; ++k) {
     if (k < n) {
       const uint32_t s = v[k] & 0xffffu, f = v[k] >> 16;
+      if (x < f) {  // the first pushes of a stream: a spread slot
+        x = spread_select(x, s, f);
+        continue;
+      }
       const float rf = __builtin_amdgcn_rcpf((float)f);
       const uint32_t xmax = ((RANS_L >> CDF_BITS) << 8) * f;
       const uint32_t b1 = x >= xmax ? 1u : 0u;
@@ -297,7 +348,7 @@ __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
   const int64_t slot_end = G.D.slot_base + A.K * (6 * G.lane_px_off + 8 * (int64_t)G.q) +
                            (G.kk + 1) * lane_slot_bytes((int64_t)G.Hl * G.Wl);
   uint8_t* out = A.slots + slot_end;
-  const uint4* src = (const uint4*)(A.rev + SL * A.rev_cap);
+  const uint4* src = (const uint4*)(A.rev + G.rev_off);
   const int64_t n = A.lane_len[SL];
   uint32_t x = RANS_X0;
   constexpr int B = 16;  // symbols per batch; the next batch loads while this one is coded
@@ -321,11 +372,11 @@ __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
     for (int k = 0; k < B; ++k) va[k] = vb[k];
     na = nb;
   }
-  out -= 4;
-  out[0] = (uint8_t)x;
-  out[1] = (uint8_t)(x >> 8);
-  out[2] = (uint8_t)(x >> 16);
-  out[3] = (uint8_t)(x >> 24);
+  // the final state's significant bytes (x >= 1), most significant first
+  do {
+    *--out = (uint8_t)x;
+    x >>= 8;
+  } while (x != 0u);
   A.lane_len[SL] = (uint32_t)((A.slots + slot_end) - out);
 }
 
@@ -588,6 +639,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
          C[5] == (uint8_t)(A.order == 0 ? 0 : 1) && C[6] == (uint8_t)H_ && C[7] == (uint8_t)K && rd_u32(C + 8) == (uint32_t)D.H &&
          rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
          (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
+    // the streams fill the container exactly: the last end is its payload
+    ok = ok && pay + (int64_t)rd_u32(C + HDR_BYTES + 4 * ((int64_t)nl * K - 1)) == clen;
     ok = uniform(ok ? 1 : 0) != 0;
     if (ok) {
       const uint64_t hsh = (uint64_t)rd_u32(C + 20) | ((uint64_t)rd_u32(C + 24) << 32);
@@ -613,7 +666,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     if (ok) {
       lend = rd_u32(C + HDR_BYTES + 4 * e);
       lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
-      okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+      okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
     }
     ok = __ballot(okr) == ~0ull;
     RS.S = C + pay + lstart;
@@ -626,7 +679,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
       if (ok) {
         lend = (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * e));
         lstart = e > 0 ? (uint32_t)uniform((int)rd_u32(C + HDR_BYTES + 4 * (e - 1))) : 0u;
-        ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 4;
+        ok = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
       }
       R[k].S = C + pay + lstart;
       R[k].len = lend - lstart;
@@ -638,15 +691,32 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   }
   if constexpr (SAMPLE) {
   } else if constexpr (K == 4) {
+    // the initial state: the stream's first bytes, most significant first,
+    // read while x < L (at most four)
     RS.fill(0, p);
-    RS.x = (uint32_t)__shfl((int)RS.word, g << 4);  // bytes 0..3, little endian
-    RS.pos = 4;
+    const uint32_t w0 = (uint32_t)__shfl((int)RS.word, g << 4);  // bytes 0..3
+    uint32_t xs = 0u, ps = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const bool rd = xs < RANS_L && ps < RS.len;
+      xs = rd ? ((xs << 8) | ((w0 >> (8 * b)) & 255u)) : xs;
+      ps += rd ? 1u : 0u;
+    }
+    RS.x = xs;
+    RS.pos = ps;
   } else {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       R[k].fill(0, lane);
-      x[k] = R[k].byte_at(0) | (R[k].byte_at(1) << 8) | (R[k].byte_at(2) << 16) | (R[k].byte_at(3) << 24);
-      pos[k] = 4;
+      uint32_t xs = 0u, ps = 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bool rd = xs < RANS_L && ps < R[k].len;
+        xs = rd ? ((xs << 8) | R[k].byte_at((uint32_t)b)) : xs;
+        ps += rd ? 1u : 0u;
+      }
+      x[k] = xs;
+      pos[k] = ps;
     }
   }
   float* prm = (float*)(piv + PIV_WORDS);
@@ -768,7 +838,10 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             const int kp = min(16 * (p + 1), 255);
             const uint32_t pq = cdf_quant(kp, cdf_eval10(kp, P));
             const uint32_t pv = p < 15 ? pq : CDF_TOTAL;
-            const uint32_t slot = RS.x & 0xffffu;
+            // a state below 2^16 (the end of the stream) holds a spread slot:
+            // the symbol is searched with its reversal
+            const bool small = RS.x < CDF_TOTAL;
+            const uint32_t slot = small ? rev16(RS.x) : (RS.x & 0xffffu);
             const int b = row_count(__ballot(pv <= slot), g);
             const int k2 = 16 * b + p;
             const uint32_t c2 = cdf_quant(k2, cdf_eval10(max(k2, 1), P));
@@ -784,7 +857,11 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
             const uint32_t np_r = (uint32_t)__shfl((int)pv, rb | b);
             const uint32_t start = (b == 0 && cnt == 0) ? 0u : st_r;
             const uint32_t freq = (cnt < 15 ? nc_r : np_r) - start;
-            const uint32_t xn = freq * (RS.x >> 16) + slot - start;
+            uint32_t xn = freq * (RS.x >> 16) + slot - start;
+            if (__ballot(small && act) != 0ull) {  // rare: a stream's last few pops
+              const uint32_t xr = spread_rank(RS.x, start, freq);
+              xn = small ? xr : xn;
+            }
             RS.x = act ? xn : RS.x;
             RS.renorm(act, p, g);
             // the symbol of pixel p (decoded by row p - q0) to all its lanes
@@ -856,7 +933,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           int sym[K];
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            slot[k] = x[k] & 0xffffu;
+            slot[k] = x[k] < CDF_TOTAL ? rev16(x[k]) : (x[k] & 0xffffu);  // spread slot below 2^16
             // bucket: pivots of the pixel at or below the slot (pv of lane p =
             // cdf at 16 (p + 1); lane 15 holds 2^16, so b <= 15)
             const int b = __popcll(__ballot(pv[k] <= slot[k]) & 0xffffull);
@@ -878,7 +955,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             const bool act = q0 + k < na;
-            const uint32_t xn = freq[k] * (x[k] >> 16) + slot[k] - start[k];
+            uint32_t xn = freq[k] * (x[k] >> 16) + slot[k] - start[k];
+            if (x[k] < CDF_TOTAL) xn = spread_rank(x[k], start[k], freq[k]);  // wave-uniform
             x[k] = act ? xn : x[k];
             R[k].renorm(x[k], pos[k], lane, act);
             if (p == q0 + k) {
@@ -1147,7 +1225,7 @@ static void launch_layout(const RansEncArgs& a, hipStream_t s) {
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
-  if (a.h < 1 || a.h > 3 || (a.K != 1 && a.K != 2 && a.K != 4) || (a.rev_cap & 15) != 0)
+  if (a.h < 1 || a.h > 3 || (a.K != 1 && a.K != 2 && a.K != 4))
     return hipErrorInvalidValue;
   const int sel = 3 * (a.h - 1) + (a.K == 1 ? 0 : a.K == 2 ? 1 : 2);
   switch (sel) {

@@ -37,10 +37,10 @@ struct RansEncArgs {
   const uint32_t* sym;
   uint8_t* slots;
   uint32_t* lane_len;      // symbols per stream (gather), then bytes per stream (encoder)
-  uint32_t* rev;           // per stream, its symbols in coding order (reverse decode order)
-  int64_t rev_cap;         // words per stream in rev, a multiple of 16
-  int32_t* after;          // per stream and step t: the stream's symbols in steps after t
-  int64_t after_cap;       // entries per stream in after (more than any lane's steps)
+  uint32_t* rev;           // per stream, its symbols in coding order (reverse decode order);
+                           // image n's streams from desc[n].rev_base, stream_rev_words each
+  int32_t* after;          // per stream and step t: the stream's symbols in steps after t;
+                           // from desc[n].after_base, stream_after_entries each
   int64_t max_lane_px;     // pixels of the largest lane
 };
 

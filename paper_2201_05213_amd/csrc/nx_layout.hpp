@@ -14,7 +14,7 @@ constexpr int HEAD_TILES = 8;     // head rows padded to 8 MFMA tiles of 16
 constexpr int CDF_BITS = 16;
 constexpr uint32_t CDF_TOTAL = 1u << CDF_BITS;
 constexpr uint32_t RANS_L = 1u << 23;  // lower bound of the normalised rANS state
-constexpr uint32_t RANS_X0 = 1u;       // encoder start state
+constexpr uint32_t RANS_X0 = 1u;       // encoder start state (the decoder's end state)
 
 // number of causal taps of the (2h+1)x(2h+1) first kernel: h rows of 2h+1,
 // plus h to the left in the pixel's own row
@@ -61,8 +61,23 @@ struct ImgDesc {
   int32_t pad_;
   int64_t slot_base;   // byte offset of this image's first rANS lane slot
   uint64_t seed;       // sampling: key word 0 of the image's Philox stream
+  int64_t rev_base;    // encoder: first word of this image's streams in the coding-order symbol buffer
+  int64_t after_base;  // encoder: first entry of this image's streams in the per-step offset table
 };
-static_assert(sizeof(ImgDesc) == 80, "descriptor layout");
+static_assert(sizeof(ImgDesc) == 96, "descriptor layout");
+
+// Encoder scratch per rANS stream of a lane of at most ph x pw pixels (K
+// streams per lane): its symbols in coding order, 3 (ph pw / K + T) words
+// rounded up to 16 (a stream holds at most ceil(n / K) + 1 rows of a step of
+// n rows; T = pw + (h + 1)(ph - 1) steps with h + 1 <= 4), and per step the
+// count of its symbols in later steps (T + 1 entries). Each image's streams
+// take these sizes for its own patch shape, so the buffers grow with the sum
+// of the lanes, not with the largest lane times their number.
+NXHD int64_t stream_rev_words(int ph, int pw, int K) {
+  const int64_t cap = 3 * (((int64_t)ph * pw + K - 1) / K + pw + 4 * ((int64_t)ph - 1));
+  return (cap + 15) / 16 * 16;
+}
+NXHD int64_t stream_after_entries(int ph, int pw) { return (int64_t)pw + 4 * ((int64_t)ph - 1) + 1; }
 
 // Sheared layout (Sec. 3.1, Algorithm 2): a decoding wave keeps the last
 // RING_COLS columns of its lane's sheared canvas (column t = wavefront step
@@ -83,12 +98,13 @@ NXHD int64_t ring_windows(int grid, int waves) {
 
 // Container header (little endian), followed by u32 end[n_lanes * K]
 // (cumulative payload bytes per stream, stream k of lane q at q K + k) and
-// the stream payloads (4 final-state bytes, then the renormalisation bytes in
-// the order the decoder reads them).
+// the stream payloads (the final state's significant bytes, most significant
+// first, then the renormalisation bytes in the order the decoder reads them).
 constexpr int HDR_BYTES = 32;
-constexpr uint8_t CONTAINER_VERSION = 1;
+constexpr uint8_t CONTAINER_VERSION = 2;
 // coder byte = K, the rANS streams per lane: byte-renormalising rANS,
-// L = 2^23, M = 2^16, start state 1, K in {1, 2, 4}
+// L = 2^23, M = 2^16, start state 1, pushes from states below the symbol's
+// frequency through its bit-reversal-spread slots, K in {1, 2, 4}
 constexpr uint8_t CODER_RANS8 = 1;
 constexpr int MAX_INTERLEAVE = 4;
 NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4; }
@@ -96,7 +112,7 @@ NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4; }
 // 16 u16 patch_h (0 = whole) | 18 u16 patch_w (0 = whole) | 20 u64 model hash
 // 28 u32 n_lanes
 
-// Lane slot for the rANS encoder: at most 2 bytes per symbol, 4 flush bytes.
+// Lane slot for the rANS encoder: at most 2 bytes per symbol, at most 4 flush bytes.
 inline constexpr int64_t lane_slot_bytes(int64_t px) { return 6 * px + 8; }
 
 // ------------------------------------------------------------------ parameters

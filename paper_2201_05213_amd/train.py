@@ -20,7 +20,7 @@ import torch
 
 from ._lib import NelloxError, check, load
 
-__all__ = ["param_count", "nll_bits", "NLLFunction", "random_crops", "bits_per_dim", "fit"]
+__all__ = ["param_count", "nll_bits", "nll_bits_per_px", "NLLFunction", "random_crops", "bits_per_dim", "fit"]
 
 
 def _dims(dims) -> ctypes.Array:
@@ -60,7 +60,7 @@ class NLLFunction(torch.autograd.Function):
         ws = torch.empty(nb, dtype=torch.uint8, device=params.device)
         bits = torch.empty(n, dtype=torch.float64, device=params.device)
         stream = ctypes.c_void_p(torch.cuda.current_stream(params.device).cuda_stream)
-        check(L.nellox_nll_fwd_train(params.data_ptr(), d, imgs.data_ptr(), n, H, W, bits.data_ptr(),
+        check(L.nellox_nll_fwd_train(params.data_ptr(), d, imgs.data_ptr(), n, H, W, bits.data_ptr(), None,
                                      ws.data_ptr(), ws.numel(), stream), "nellox_nll_fwd_train")
         ctx.save_for_backward(params, imgs)
         ctx.dims = tuple(int(v) for v in dims)
@@ -69,6 +69,10 @@ class NLLFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_bits: torch.Tensor):
+        if ctx.ws is None:
+            # the workspace holding the forward's activations is released
+            # after the first backward
+            raise RuntimeError("nll_bits: a second backward through the same graph is not supported")
         params, imgs = ctx.saved_tensors
         L = load()
         n, H, W = (int(v) for v in imgs.shape[:3])
@@ -84,6 +88,25 @@ class NLLFunction(torch.autograd.Function):
 def nll_bits(params: torch.Tensor, dims, imgs: torch.Tensor) -> torch.Tensor:
     """Code length in bits of each image (float64, shape (N,)); differentiable in params."""
     return NLLFunction.apply(params, dims, imgs)
+
+
+def nll_bits_per_px(params: torch.Tensor, dims, imgs: torch.Tensor) -> torch.Tensor:
+    """Each pixel's code length -log2 p in bits as the training forward
+    computes it (float32, shape (N, H, W)); not differentiable."""
+    _check_inputs(params, dims, imgs)
+    L = load()
+    n, H, W = (int(v) for v in imgs.shape[:3])
+    d = _dims(dims)
+    nb = L.nellox_train_workspace_bytes(d, n, H, W)
+    if nb == 0:
+        raise NelloxError(1, "nellox_train_workspace_bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=params.device)
+    bits = torch.empty(n, dtype=torch.float64, device=params.device)
+    px = torch.empty((n, H, W), dtype=torch.float32, device=params.device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(params.device).cuda_stream)
+    check(L.nellox_nll_fwd_train(params.data_ptr(), d, imgs.data_ptr(), n, H, W, bits.data_ptr(), px.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), stream), "nellox_nll_fwd_train")
+    return px
 
 
 def random_crops(pool: torch.Tensor, batch: int, crop: int, rng) -> torch.Tensor:

@@ -59,7 +59,7 @@ def test_host_only_calls(lib):
     assert b"blob" in L.nellox_last_error()
     hdr = bytearray(32)
     hdr[0:4] = b"NLXC"
-    hdr[4], hdr[5], hdr[6], hdr[7] = 1, 1, 3, 1
+    hdr[4], hdr[5], hdr[6], hdr[7] = 2, 1, 3, 1  # container version 2
     hdr[8:12] = (200).to_bytes(4, "little")
     hdr[12:16] = (320).to_bytes(4, "little")
     hdr[16:18] = (64).to_bytes(2, "little")
@@ -70,6 +70,10 @@ def test_host_only_calls(lib):
     assert L.nellox_peek(buf, 32, ctypes.byref(H), ctypes.byref(W), ctypes.byref(oo)) == 0
     assert (H.value, W.value, oo.order, oo.patch_h, oo.patch_w) == (200, 320, 1, 64, 32)
     assert L.nellox_peek(buf, 31, ctypes.byref(H), ctypes.byref(W), ctypes.byref(oo)) == 4
+    # containers of the first format (start state 1 by ranges, four flush bytes) are refused
+    hdr[4] = 1
+    buf1 = ctypes.create_string_buffer(bytes(hdr), 32)
+    assert L.nellox_peek(buf1, 32, ctypes.byref(H), ctypes.byref(W), ctypes.byref(oo)) == 4
 
 
 def test_training_host_calls(lib):

@@ -81,15 +81,43 @@ def test_hardware_exp2_rcp_monotone(nx):
     assert r["exp2_decreasing"] == 0 and r["rcp_increasing"] == 0 and r["sigmoid_increasing"] == 0
 
 
-@pytest.mark.parametrize("name", ["A", "B"])
+# per-pixel code length: FP32 on the GPU against the oracle's FP64, within
+# 1e-5 relative, with a floor of 1e-5 bits for pixels of small code length
+PX_REL, PX_ABS = 1e-5, 1e-5
+
+
+def edge_images():
+    """Images whose values sit at the edge bins: a smooth field stretched so
+    that about a third of its values clip to 0 or 255, and uniform noise."""
+    a = synth.smooth_field_image(2.0, 3, 0, 20, 28, 905).astype(np.int32)
+    a = np.clip((a - 128) * 3 + 128, 0, 255).astype(np.uint8)
+    b = np.random.default_rng(906).integers(0, 256, size=(9, 13, 3), dtype=np.uint8)
+    b[0, :, :] = 0
+    b[-1, :, :] = 255
+    return [a, b]
+
+
+@pytest.mark.parametrize("name", ["A", "B", "C"])
 def test_nll_matches_oracle(models, name):
-    say(f"[gpu] nll vs oracle, model {name}")
+    """nellox_nll against the oracle pixel by pixel (Eq. 2 per pixel), and
+    per image; images include edge-bin values and a ragged 16-pixel tile."""
+    say(f"[gpu] nll vs oracle per pixel, model {name}")
     m, om, _ = models[name]
-    imgs = synth.workload_images("single32") + [synth.smooth_field_image(2.0, 3, 0, 24, 40, 901)]
-    tot = m.nll([cuda(i) for i in imgs]).cpu().numpy()
+    imgs = synth.workload_images("single32") + [synth.smooth_field_image(2.0, 3, 0, 24, 40, 901)] + edge_images()
+    tot, px = m.nll([cuda(i) for i in imgs], per_pixel=True)
+    tot, px = tot.cpu().numpy(), px.cpu().numpy().astype(np.float64)
+    o = 0
+    worst = 0.0
     for k, img in enumerate(imgs):
-        ref = om.stats(img)["cbits"]
-        assert abs(tot[k] - ref) <= 1e-5 * ref, (tot[k], ref)
+        H, W = img.shape[:2]
+        ref = om.stats(img, px_bits=True)
+        got = px[o:o + H * W].reshape(H, W)
+        o += H * W
+        err = np.abs(got - ref["px_bits"])
+        assert np.all(err <= PX_REL * np.abs(ref["px_bits"]) + PX_ABS), (k, float(err.max()))
+        worst = max(worst, float((err / np.abs(ref["px_bits"])).max()))
+        assert abs(tot[k] - ref["cbits"]) <= 1e-5 * ref["cbits"], (tot[k], ref["cbits"])
+    say(f"  worst per-pixel relative difference {worst:.2e}")
 
 
 @pytest.mark.parametrize("order", [0, 1])
@@ -487,3 +515,23 @@ def test_whole_image_lanes_above_one_scatter_chunk(models, nx, order, K):
         assert torch.equal(a, b)
     sym, _ = m.debug_symbols(ts)
     assert torch.equal(sym, dump)
+
+
+def test_workspace_scales_with_the_sum_of_lanes(models, nx):
+    """A mixed batch (one unpatched 2048x1536 image and 511 images of 32x32)
+    needs workspace in proportion to its pixels, not to its lane count times
+    its largest lane; decoding needs a small part of it."""
+    import ctypes
+
+    m, _, _ = models["B"]
+    L = nx.load()
+    shapes = [(2048, 1536)] + [(32, 32)] * 511
+    arr = (nx._lib.NelloxImage * len(shapes))(*[nx._lib.NelloxImage(None, h, w) for h, w in shapes])
+    npx = sum(h * w for h, w in shapes)
+    for K in (1, 4):
+        o = nx._opts(nx.WAVEFRONT, None, K)
+        full = L.nellox_workspace_bytes(m._h, len(shapes), arr, ctypes.byref(o))
+        dec = L.nellox_decode_workspace_bytes(m._h, len(shapes), arr, ctypes.byref(o))
+        say(f"[gpu] workspace K={K}: {full / npx:.1f} B/px (decode {dec / npx:.1f} B/px)")
+        assert 0 < dec < full <= (28 + 6 * K + 20) * npx
+        assert dec <= 8 * npx + (1 << 20)

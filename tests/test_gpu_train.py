@@ -3,9 +3,10 @@
 The HIP path (nellox_nll_fwd_train / nellox_nll_bwd through the C ABI)
 against the FP64 torch reference (oracle/torch_ref.py, itself pinned to
 finite differences and to the C oracle on the CPU). Bars: code length
-within 1e-5 relative; gradient within 1e-4 relative (norm of the
-difference over the norm of the reference, over the whole vector and per
-tensor).
+within 1e-5 relative per image and per pixel (with a floor of 1e-5 bits);
+gradient within 1e-4 relative: the norm of the difference over the norm of
+the reference, over the whole vector and per tensor, and every element
+within 1e-4 |g| + 1e-6 max |g|.
 """
 import sys
 
@@ -86,6 +87,21 @@ def compare(dims, params, imgs, weights, tr, label):
     assert err <= GRAD_TOL
     for n, e in per.items():
         assert e <= GRAD_TOL, (n, e)
+    # element by element: an error confined to small weights cannot hide in a norm
+    bound = GRAD_TOL * np.abs(rg) + 1e-6 * np.abs(rg).max()
+    bad = np.abs(gg - rg) > bound
+    say(f"  per element: worst |diff| / bound {float((np.abs(gg - rg) / bound).max()):.3f}")
+    assert not bad.any(), (int(bad.sum()), np.flatnonzero(bad)[:8])
+    # per-pixel code length of the training forward against the FP64 joint likelihood
+    h, C, nb, _ = dims
+    pxg = train.nll_bits_per_px(torch.from_numpy(params).cuda(), dims,
+                                torch.from_numpy(np.ascontiguousarray(imgs)).cuda()).cpu().numpy().astype(np.float64)
+    with torch.no_grad():
+        x = torch.from_numpy(np.ascontiguousarray(imgs))
+        th = torch_ref.theta(torch.from_numpy(params.astype(np.float64)), h, C, nb, x)
+        pxr = (-torch_ref.joint_log_prob(th, x) / np.log(2.0)).numpy()
+    perr = np.abs(pxg - pxr)
+    assert np.all(perr <= BITS_TOL * np.abs(pxr) + 1e-5), float(perr.max())
     # masked taps of the first kernel get no gradient
     h, C, _, _ = dims
     K = 2 * h + 1

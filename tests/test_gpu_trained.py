@@ -1,22 +1,23 @@
 """Coded bits of a trained model against the FP64 oracle's quantised ideal.
 
-Model B is trained by the training configuration (2000 Adam steps, lr 1e-3,
-64 random 32x32 crops per step from 512 smooth 64x64 images; seeds as in the
-input recipe) to about 3.1 bits/dim, then the benchmark's workloads are coded
-with it: 32x32 images as whole lanes (the 512-image batch), the uneven batch
-with 32x32 and 64x64 patches, and the large batch with 64x64 patches and
-with the benchmark's (64 columns, the height from tune.balanced_patch: 86
-rows on 256 CUs), with one and with four rANS streams per lane. Coded bits (the lane payloads) are
-compared with the oracle's quantised ideal -sum log2(f / 2^16) of the same
-lanes (sampled lanes for the large images).
+Model B after the training configuration (2000 Adam steps, lr 1e-3, 64
+random 32x32 crops per step from 512 smooth 64x64 images; seeds as in the
+input recipe), trained on the CPU with the oracle's FP64 formulation of the
+code length (tests/golden/make_trained_model_b.py writes the blob, so no
+input of the oracle comes from the library), codes the benchmark's
+workloads: 32x32 images as whole lanes (the 512-image batch), the uneven
+batch with 32x32 and 64x64 patches, and the large batch with 64x64 patches
+and with the benchmark's (64 columns, the height from tune.balanced_patch:
+86 rows on 256 CUs), with one and with four rANS streams per lane. Coded bits
+(the lane payloads) are compared with the oracle's quantised ideal -sum
+log2(f / 2^16) of the same lanes (sampled lanes for the large images).
 
-Every rANS stream costs a fixed ~15-16 bits over its ideal: the 4-byte flush
-of the final state (up to 9 bits more than its information) and the first
-symbol coded into the trimmed start state. So the relative gap grows as bits
-per stream shrink. The 0.1% bar holds for one stream on 64x64 lanes and
-for four streams on the benchmark's lanes; the test asserts both, reports
-the rest, and checks that every gap is within 20 bits per stream.
+A stream costs about 5 bits over its ideal (its start state, about one bit,
+and the rounding of its flush to whole bytes): the 0.1% bar holds for every
+row except four streams on 32x32 lanes, whose ~12 kbit would need under 3
+bits per stream; there the test asserts the per-stream cost instead.
 """
+import os
 import sys
 
 import numpy as np
@@ -34,19 +35,16 @@ def say(msg):
     sys.stdout.flush()
 
 
+TRAINED_B = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "model_b_trained.nlxw")
+
+
 @pytest.fixture(scope="module")
 def trained():
     import paper_2201_05213_amd as nx
-    from paper_2201_05213_amd import blob, train
 
     torch.cuda.set_device(0)
-    b, _ = synth.model_blob("B")
-    dims, params = blob.params_from_blob(b)
-    pool = torch.from_numpy(synth.training_pool(n=512)).cuda()
-    p = train.fit(torch.from_numpy(params).cuda(), dims, pool, 2000, np.random.Generator(np.random.PCG64(5_999_999)))
-    tb = blob.blob_from_params(dims, p.cpu().numpy())
-    held = torch.from_numpy(synth.training_pool(n=64, seed_base=5_500_000)).cuda()
-    say(f"[gpu] trained model B: held-out bits/dim {train.bits_per_dim(p, dims, held):.4f}")
+    with open(TRAINED_B, "rb") as f:
+        tb = f.read()
     return nx, nx.Model(tb), oracle.Model.from_blob(tb)
 
 
@@ -120,9 +118,8 @@ def test_trained_gap(trained, case):
         per_lane = (got - ideal) / n
         say(f"[gpu] trained B, {name}, {K} stream(s): {n} lanes, {ideal / n:.0f} ideal bits per lane, "
             f"{got / dims:.4f} bits/dim coded, gap {100 * gap:.4f}% ({per_lane:.1f} bits per lane)")
-        # each stream costs its flush and start, and nothing else
-        assert 0.0 <= per_lane <= 20.0 * K, per_lane
-    if patch == (64, 64):
-        assert (res[1] - ideal) / ideal <= 1e-3
-    if CASES[case][2] == "bench":
-        assert (res[4] - ideal) / ideal <= 1e-3
+        # each stream costs its start state and flush rounding, and nothing else
+        assert -2.0 * K <= per_lane <= 10.0 * K, per_lane
+        small = imgs[0].shape[0] * imgs[0].shape[1] <= 32 * 32 or patch == (32, 32)
+        if not (small and K == 4):
+            assert gap <= 1e-3, (K, gap)
