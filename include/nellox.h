@@ -146,6 +146,20 @@ nellox_status nellox_decode(const nellox_model* m, int32_t n, const uint8_t* in,
                             const nellox_opts* opts, const nellox_image* out, int32_t* status, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* As nellox_decode, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): no
+ * workspace argument, and no device or pinned allocation on the call. The
+ * decoder's scratch (image descriptors, the lane queue, the sheared layout's
+ * context windows) lives in a 32 MiB device array of the library, one per
+ * GPU, held until the process ends; its address is looked up on the first
+ * call on each device. The call refuses (NELLOX_E_CAPACITY) a batch whose
+ * scratch exceeds 32 MiB (nellox_decode_workspace_bytes tells) or that has
+ * more than 2,730 images. Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must
+ * not be made; every call resets what it needs (queue, windows) itself. */
+nellox_status nellox_decode_static(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
+                                   const nellox_opts* opts, const nellox_image* out, int32_t* status, void* stream);
+
 /* As nellox_decode, and also writes the (start | freq << 16) the decoder used
  * for every pixel and channel to sym_dump (device, sum of H*W*3 uint32, images
  * in order) -- for bitwise comparison with nellox_debug_symbols. */

@@ -42,6 +42,7 @@ SIGNATURES = {
     "nellox_peek": (_ST, [_P, _SZ, _P, _P, _P]),
     "nellox_decode": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_decode_trace": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "nellox_decode_static": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "nellox_decode_prepare": (_ST, [_P, _I32, _P, _P, _P, _SZ, _P, _P]),
     "nellox_decode_run": (_ST, [_P, _P, _P, _P, _P, _P, _P]),
     "nellox_sample": (_ST, [_P, _I32, _P, _P, _P, _P, _SZ, _P]),

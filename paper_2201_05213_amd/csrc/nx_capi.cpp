@@ -47,6 +47,10 @@ int padded_channels(int C) { return C <= 16 ? 16 : C <= 32 ? 32 : C <= 64 ? 64 :
 
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
+// pinned plan staging allocated with the model, so that the no-allocation
+// decoder never has to grow it: descriptors of up to 2,730 images
+constexpr size_t STAGING_BYTES = (size_t)256 << 10;
+
 }  // namespace
 
 struct nellox_model {
@@ -389,6 +393,13 @@ nellox_status nellox_model_create(const void* blob, size_t nbytes, nellox_model*
   m->staging_bytes = 0;
   e = hipMalloc(&m->dw, img.size() * 4);
   if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(weights)"); }
+  e = hipHostMalloc(&m->staging, STAGING_BYTES, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(m->dw);
+    delete m;
+    return hip_fail(e, "hipHostMalloc(plan staging)");
+  }
+  m->staging_bytes = STAGING_BYTES;
   e = hipMemcpy(m->dw, img.data(), img.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(m->staged, nullptr);
@@ -615,6 +626,30 @@ nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nell
 nellox_status nellox_decode_run(const nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
                                 const uint64_t* in_offsets, int32_t* status, void* ws, void* stream) {
   return run_impl(const_cast<nellox_model*>(m), plan, in, in_offsets, status, nullptr, ws, stream);
+}
+
+nellox_status nellox_decode_static(const nellox_model* mc, int32_t n, const uint8_t* in, const uint64_t* in_offsets,
+                                   const nellox_opts* o, const nellox_image* out, int32_t* status, void* stream) {
+  nellox_model* m = const_cast<nellox_model*>(mc);
+  if (check_model(m)) return NELLOX_E_ARG;
+  if (n > 0 && (!in || !in_offsets || !status)) return fail(NELLOX_E_ARG, "null pointer argument");
+  Plan P;
+  nellox_status st = make_plan(n, out, o, P, true);
+  if (st) return st;
+  plan_ring(m, P);
+  const WsLayout W = ws_layout(P, n);
+  if (W.small > (int64_t)STATIC_SCRATCH_BYTES)
+    return fail(NELLOX_E_CAPACITY, "this batch needs " + std::to_string(W.small) +
+                                       " bytes of decoder scratch, more than the " +
+                                       std::to_string(STATIC_SCRATCH_BYTES) +
+                                       " the no-allocation decoder has (use nellox_decode with a workspace)");
+  if (sizeof(ImgDesc) * (size_t)n > STAGING_BYTES)
+    return fail(NELLOX_E_CAPACITY, "the no-allocation decoder takes at most " +
+                                       std::to_string(STAGING_BYTES / sizeof(ImgDesc)) + " images per call");
+  void* ws = nullptr;
+  hipError_t e = static_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "scratch address (hipGetSymbolAddress)");
+  return decode_impl(m, n, in, in_offsets, o, out, status, nullptr, ws, STATIC_SCRATCH_BYTES, stream);
 }
 
 nellox_status nellox_decode_trace(const nellox_model* m, int32_t n, const uint8_t* in, const uint64_t* in_offsets,

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "nx_device.hpp"
 #include "nx_kernels.hpp"
 #include "nx_order.hpp"
@@ -1270,6 +1272,30 @@ hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits,
 }  // namespace nx
 
 namespace nx {
+// Scratch of the no-allocation decoder: a file-scope device array that every
+// GPU the library runs on holds until the process ends. In host code its name
+// is only a stand-in; the device address of each GPU's copy is looked up once
+// per device (with that device current) and kept.
+static __device__ __align__(256) uint8_t scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
 hipError_t launch_check_monotone(unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(k_zero4, dim3(1), dim3(64), 0, s, out);
   const uint64_t threads = (MONO_ALL + MONO_CHUNK - 1) / MONO_CHUNK;

@@ -145,6 +145,12 @@ constexpr int REDUCE_PARTS = 64;
 hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* partials, double* out,
                               hipStream_t s);
 
+// the no-allocation decoder's scratch: STATIC_SCRATCH_BYTES of device memory
+// per GPU (a file-scope array); static_scratch gives the current device's
+// address, looked up on the first call per device
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+hipError_t static_scratch(void** ptr);
+
 // exhaustive order check of the hardware exp2 and reciprocal (out: 4 counters)
 hipError_t launch_check_monotone(unsigned long long* out, hipStream_t s);
 
