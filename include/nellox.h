@@ -19,7 +19,7 @@
  *   from a state below the symbol's frequency f takes the x-th of the slots
  *   whose 16-bit reversal lies in the symbol's range, so it grows the state
  *   by about 2^16 / f; the final state is flushed as its significant bytes),
- *   one stream per lane or K = 2, 4 interleaved streams per lane (opts.interleave):
+ *   one stream per lane or K = 2, 4, 8, 16 interleaved streams per lane (opts.interleave):
  *   in a wavefront step, row i - i_first goes to stream (i - i_first) mod K.
  *   Decoding order (nellox_opts.order):
  *     0 raster: one pixel after the other (the sequential decoder of Sec. 2);
@@ -75,11 +75,12 @@ typedef struct {
                          sheared canvas, where every step is one column */
   int32_t patch_h;    /* patch rows; <= 0 or >= H: whole image */
   int32_t patch_w;    /* patch columns; <= 0 or >= W: whole image */
-  int32_t interleave; /* rANS states per lane: 0 or 1 = one; 2 or 4 (wavefront order
-                         only): the rows of every wavefront step are dealt to the
-                         states in turn, so a decoder can search that many symbols
-                         at once; each extra state costs one stream's start and
-                         flush, a few bits */
+  int32_t interleave; /* rANS states per lane: 0 or 1 = one; 2, 4, 8 or 16 (wavefront
+                         order only): the rows of every wavefront step are dealt to
+                         the states in turn, so a decoder can search that many
+                         symbols at once (with 16, every row of a 16-row group has
+                         its own stream); each extra state costs one stream's start
+                         and flush, about 4.6 bits */
 } nellox_opts;
 
 typedef struct {

@@ -123,7 +123,7 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     return fail(NELLOX_E_ARG, "order must be 0 (raster), 1 (wavefront) or 2 (wavefront, sheared layout)");
   P.order = o->order;
   P.K = o->interleave <= 1 ? 1 : o->interleave;
-  if (!valid_interleave(P.K)) return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2 or 4");
+  if (!valid_interleave(P.K)) return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2, 4, 8 or 16");
   if (P.K > 1 && o->order == 0) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
   P.d.resize(n);
   for (int k = 0; k < n; ++k) {

@@ -605,8 +605,18 @@ struct RowStream {
   }
 };
 
+// K >= 8: one stream per pixel row of a 16-row group (K = 16), or one per
+// pair of rows p and p + 8 (K = 8); lane (p, g) holds stream p mod K's state,
+// the same in every lane of the pixel (and, for K = 8, of both rows)
+struct PixStream {
+  gbytes S;
+  uint32_t len, pos, x;
+};
+
 // K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
-// streams k) per iteration, their searches independent of each other.
+// streams k) per iteration, their searches independent of each other;
+// K >= 8: every row of a group pops from its own stream at once, found by a
+// bisection of the quantised CDF over the whole group.
 // SAMPLE: ancestral sampling instead of decoding (no container): each
 // symbol is the inverse quantised CDF at its Philox slot, found by bisection
 // for all rows of a group at once (their slots do not depend on each other).
@@ -655,12 +665,26 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     return;
   }
   // K <= 2: the streams' states are scalar (one search after another);
-  // K = 4: one stream per 16-lane row, its state held by the row
-  constexpr int KS = K == 4 ? 1 : K;
+  // K = 4: one stream per 16-lane row, its state held by the row;
+  // K >= 8: one stream per pixel (per pair of pixels for K = 8)
+  constexpr int KS = K <= 2 ? K : 1;
   ByteStage R[KS];
   uint32_t x[KS], pos[KS];
   RowStream RS;
+  PixStream PS;
   if constexpr (SAMPLE) {
+  } else if constexpr (K >= 8) {
+    const int64_t e = (int64_t)q * K + (p & (K - 1));  // stream table entry of this pixel row
+    uint32_t lend = 0, lstart = 0;
+    bool okr = ok;
+    if (ok) {
+      lend = rd_u32(C + HDR_BYTES + 4 * e);
+      lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
+      okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
+    }
+    ok = __ballot(okr) == ~0ull;
+    PS.S = as_global(C + pay + lstart);
+    PS.len = lend - lstart;
   } else if constexpr (K == 4) {
     const int64_t e = (int64_t)q * K + g;  // stream table entry of this row
     uint32_t lend = 0, lstart = 0;
@@ -692,6 +716,19 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
     return;
   }
   if constexpr (SAMPLE) {
+  } else if constexpr (K >= 8) {
+    // the initial state: the stream's first bytes, most significant first,
+    // read while x < L (at most four; loads clamped into the stream)
+    uint32_t xs = 0u, ps = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t byte = PS.S[min((uint32_t)b, PS.len - 1u)];
+      const bool rd = xs < RANS_L && ps < PS.len;
+      xs = rd ? ((xs << 8) | byte) : xs;
+      ps += rd ? 1u : 0u;
+    }
+    PS.x = xs;
+    PS.pos = ps;
   } else if constexpr (K == 4) {
     // the initial state: the stream's first bytes, most significant first,
     // read while x < L (at most four)
@@ -814,6 +851,68 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           if (c == 0) xv[0] = lo;
           else if (c == 1) xv[1] = lo;
           else xv[2] = lo;
+        } else if constexpr (K >= 8) {
+          // every pixel's symbol from its own stream: eight halvings of [0,
+          // 256] over the group at once, each the encoder's evaluation of the
+          // quantised CDF (cdf_eval), keeping the bracket's CDF values, so
+          // (start, freq) are bitwise the encoder's; K = 8 pops rows 0..7,
+          // then rows 8..15
+#pragma unroll
+          for (int half = 0; half < 16 / K; ++half) {
+            const int q0 = half * K;
+            if (q0 >= na) break;
+            const bool act = p >= q0 && p < q0 + K && p < na;
+            // the two bytes a renormalisation may read, fetched ahead of the
+            // search (clamped into the stream, used only while bytes remain)
+            const uint32_t lm = PS.len - 1u;
+            const uint32_t nb0 = PS.S[min(PS.pos, lm)];
+            const uint32_t nb1 = PS.S[min(PS.pos + 1u, lm)];
+            // a state below 2^16 (the end of the stream) holds a spread slot
+            const bool small = PS.x < CDF_TOTAL;
+            const uint32_t slot = small ? rev16(PS.x) : (PS.x & 0xffffu);
+            int lo = 0, hi = 256;
+            uint32_t clo = 0u, chi = CDF_TOTAL;
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+              const int mid = (lo + hi) >> 1;
+              const uint32_t v = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b));
+              const bool le = v <= slot;
+              lo = le ? mid : lo;
+              clo = le ? v : clo;
+              hi = le ? hi : mid;
+              chi = le ? chi : v;
+            }
+            const uint32_t freq = chi - clo;
+            uint32_t xn = freq * (PS.x >> 16) + slot - clo;
+            if (__ballot(small && act) != 0ull) {  // rare: a stream's last few pops
+              const uint32_t xr = spread_rank(PS.x, clo, freq);
+              xn = small ? xr : xn;
+            }
+            uint32_t pn = PS.pos;
+            const bool r0 = xn < RANS_L && pn < PS.len;
+            xn = r0 ? ((xn << 8) | nb0) : xn;
+            pn += r0 ? 1u : 0u;
+            const bool r1 = xn < RANS_L && pn < PS.len;
+            xn = r1 ? ((xn << 8) | nb1) : xn;
+            pn += r1 ? 1u : 0u;
+            PS.x = act ? xn : PS.x;
+            PS.pos = act ? pn : PS.pos;
+            if (act) {
+              if (c == 0) xv[0] = lo;
+              else if (c == 1) xv[1] = lo;
+              else xv[2] = lo;
+            }
+            if (TRACE && act && g == 0)
+              dump[((int64_t)(y0 + i) * D.W + (x0 + j)) * 3 + c] = clo | (freq << 16);
+            if constexpr (K == 8) {
+              // rows p and p + 8 share a stream: the other half takes the new state
+              const uint32_t ox = (uint32_t)__shfl_xor((int)PS.x, 8);
+              const uint32_t op = (uint32_t)__shfl_xor((int)PS.pos, 8);
+              const bool mine = p >= q0 && p < q0 + K;
+              PS.x = mine ? PS.x : ox;
+              PS.pos = mine ? PS.pos : op;
+            }
+          }
         } else if constexpr (K == 4) {
           // stage the channel's mixtures: lane (p, g) holds components g + 4 j
           float* mine = prm + p * PRM_STRIDE;
@@ -1000,6 +1099,8 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   }
   bool clean = true;
   if constexpr (SAMPLE) {
+  } else if constexpr (K >= 8) {
+    clean = __ballot(PS.x == RANS_X0 && PS.pos == PS.len) == ~0ull;
   } else if constexpr (K == 4) {
     clean = __ballot(RS.x == RANS_X0 && RS.pos == RS.len) == ~0ull;
   } else {
@@ -1166,6 +1267,8 @@ template <int H_, int C_>
 static hipError_t decode_setup(int K) {
   if (K == 2) return decode_setup_k<H_, C_, 2>();
   if (K == 4) return decode_setup_k<H_, C_, 4>();
+  if (K == 8) return decode_setup_k<H_, C_, 8>();
+  if (K == 16) return decode_setup_k<H_, C_, 16>();
   return decode_setup_k<H_, C_, 1>();
 }
 
@@ -1183,6 +1286,8 @@ template <int H_, int C_>
 static hipError_t decode_t(const DecArgs& a, int grid, int waves, hipStream_t s) {
   if (a.K == 2) return decode_k<H_, C_, 2>(a, grid, waves, s);
   if (a.K == 4) return decode_k<H_, C_, 4>(a, grid, waves, s);
+  if (a.K == 8) return decode_k<H_, C_, 8>(a, grid, waves, s);
+  if (a.K == 16) return decode_k<H_, C_, 16>(a, grid, waves, s);
   return decode_k<H_, C_, 1>(a, grid, waves, s);
 }
 
@@ -1227,19 +1332,24 @@ static void launch_layout(const RansEncArgs& a, hipStream_t s) {
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
-  if (a.h < 1 || a.h > 3 || (a.K != 1 && a.K != 2 && a.K != 4))
-    return hipErrorInvalidValue;
-  const int sel = 3 * (a.h - 1) + (a.K == 1 ? 0 : a.K == 2 ? 1 : 2);
-  switch (sel) {
+  if (a.h < 1 || a.h > 3 || !valid_interleave(a.K)) return hipErrorInvalidValue;
+  const int kx = a.K == 1 ? 0 : a.K == 2 ? 1 : a.K == 4 ? 2 : a.K == 8 ? 3 : 4;
+  switch (5 * (a.h - 1) + kx) {
     case 0: launch_layout<2, 1>(a, s); break;
     case 1: launch_layout<2, 2>(a, s); break;
     case 2: launch_layout<2, 4>(a, s); break;
-    case 3: launch_layout<3, 1>(a, s); break;
-    case 4: launch_layout<3, 2>(a, s); break;
-    case 5: launch_layout<3, 4>(a, s); break;
-    case 6: launch_layout<4, 1>(a, s); break;
-    case 7: launch_layout<4, 2>(a, s); break;
-    default: launch_layout<4, 4>(a, s); break;
+    case 3: launch_layout<2, 8>(a, s); break;
+    case 4: launch_layout<2, 16>(a, s); break;
+    case 5: launch_layout<3, 1>(a, s); break;
+    case 6: launch_layout<3, 2>(a, s); break;
+    case 7: launch_layout<3, 4>(a, s); break;
+    case 8: launch_layout<3, 8>(a, s); break;
+    case 9: launch_layout<3, 16>(a, s); break;
+    case 10: launch_layout<4, 1>(a, s); break;
+    case 11: launch_layout<4, 2>(a, s); break;
+    case 12: launch_layout<4, 4>(a, s); break;
+    case 13: launch_layout<4, 8>(a, s); break;
+    default: launch_layout<4, 16>(a, s); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -104,10 +104,10 @@ constexpr int HDR_BYTES = 32;
 constexpr uint8_t CONTAINER_VERSION = 2;
 // coder byte = K, the rANS streams per lane: byte-renormalising rANS,
 // L = 2^23, M = 2^16, start state 1, pushes from states below the symbol's
-// frequency through its bit-reversal-spread slots, K in {1, 2, 4}
+// frequency through its bit-reversal-spread slots, K in {1, 2, 4, 8, 16}
 constexpr uint8_t CODER_RANS8 = 1;
-constexpr int MAX_INTERLEAVE = 4;
-NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4; }
+constexpr int MAX_INTERLEAVE = 16;
+NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16; }
 //  0 "NLXC" | 4 u8 version | 5 u8 order | 6 u8 h | 7 u8 K | 8 u32 H | 12 u32 W
 // 16 u16 patch_h (0 = whole) | 18 u16 patch_w (0 = whole) | 20 u64 model hash
 // 28 u32 n_lanes

@@ -90,14 +90,15 @@ def test_cdf_nll_and_gap(nx, dims):
 
 @pytest.mark.parametrize("dims", DIMS, ids=ids)
 def test_round_trips_all_orders(nx, dims):
-    say(f"[gpu] dims {ids(dims)}: round trips, raster / wavefront / sheared, K = 1 and 4")
+    say(f"[gpu] dims {ids(dims)}: round trips, raster / wavefront / sheared, K = 1, 4, 8, 16")
     m, _, _ = models(nx, dims)
     shapes = [(37, 29), (1, 19), (23, 1), (40, 40)]
     imgs = [synth.smooth_field_image(2.0, 3, 2, H, W, 5200 + 7 * dims[3] + k) for k, (H, W) in enumerate(shapes)]
     ts = [cuda(i) for i in imgs]
     for patch in (None, (16, 12)):
         enc, _ = m.debug_symbols(ts, patch=patch)
-        for order, K in [(nx.RASTER, 1), (nx.WAVEFRONT, 1), (nx.WAVEFRONT, 4), (nx.SHEARED, 1), (nx.SHEARED, 4)]:
+        for order, K in [(nx.RASTER, 1), (nx.WAVEFRONT, 1), (nx.WAVEFRONT, 4), (nx.SHEARED, 1), (nx.SHEARED, 4),
+                         (nx.WAVEFRONT, 16), (nx.SHEARED, 8)]:
             data, offs = m.encode(ts, order=order, patch=patch, interleave=K)
             out, _, sym = m.decode(data, offs, shapes, order=order, patch=patch, interleave=K, trace=True)
             for a, b in zip(out, ts):

@@ -222,7 +222,7 @@ def test_corrupt_and_mismatch_detected(models, nx):
 
 
 # ---------------------------------------------------------------- interleaved streams
-@pytest.mark.parametrize("K", [2, 4])
+@pytest.mark.parametrize("K", [2, 4, 8, 16])
 @pytest.mark.parametrize("shape,patch", [((1, 1), None), ((1, 9), None), ((9, 1), None), ((5, 3), None),
                                          ((37, 99), (32, 32)), ((99, 37), (16, 3)), ((70, 41), (64, 64)),
                                          ((3, 200), (2, 7)), ((64, 64), None)])
@@ -238,13 +238,13 @@ def test_roundtrip_interleaved_edges(models, nx, shape, patch, K):
     assert torch.equal(out, t)
 
 
-@pytest.mark.parametrize("K", [2, 4])
+@pytest.mark.parametrize("K", [2, 4, 8, 16])
 def test_interleaved_symbols_and_gap(models, K):
-    """Streams K: decoder symbols bitwise equal to the encoder's; each extra
-    stream costs one flush (at most 16 bits over the oracle's quantised
-    ideal per stream); with K = 2 the 512 x 32x32 batch stays within 0.1% of
-    the ideal. (K = 4 on 1024-pixel lanes costs about 0.15%: it is meant
-    for large lanes.)"""
+    """Streams K: decoder symbols bitwise equal to the encoder's; each stream
+    costs its start and flush (at most 8 bits over the oracle's quantised
+    ideal per stream on average); with K = 2 and 4 the 512 x 32x32 batch (at
+    9 bits/dim) stays within 0.1% of the ideal. (More streams on 1024-pixel
+    lanes cost more: they are meant for large lanes.)"""
     say(f"[gpu] interleaved K={K}: 512 x 32x32, model B")
     m, om, _ = models["B"]
     imgs = synth.workload_images("batch512x32")
@@ -262,8 +262,8 @@ def test_interleaved_symbols_and_gap(models, K):
     gap = (got - ideal) / ideal
     per_stream = (got - ideal) / (len(sample) * K)
     say(f"[gpu] K={K}: sampled gap {gap * 100:.4f}%, {per_stream:.1f} bits over the ideal per stream")
-    assert per_stream <= 16.0
-    if K == 2:
+    assert per_stream <= 8.0
+    if K <= 4:
         assert gap <= 1e-3
 
 
@@ -415,7 +415,7 @@ def test_large6_full_size_in_bench_configuration(models, nx, patch):
     assert gap <= 1e-3
 
 
-@pytest.mark.parametrize("K", [2, 4])
+@pytest.mark.parametrize("K", [2, 4, 8, 16])
 def test_corrupt_streams_detected(models, nx, K):
     """Damage to any of a lane's K streams is reported (status 4), never a
     wrong image with status 0."""
@@ -497,7 +497,7 @@ def test_balanced_patch_launch_shape(models, nx):
         del ws
 
 
-@pytest.mark.parametrize("order,K", [(0, 1), (1, 1), (1, 2), (1, 4), (2, 4)])
+@pytest.mark.parametrize("order,K", [(0, 1), (1, 1), (1, 2), (1, 4), (2, 4), (1, 16), (2, 8)])
 def test_whole_image_lanes_above_one_scatter_chunk(models, nx, order, K):
     """Whole-image lanes larger than the 16,384 pixels one encoder scatter
     workgroup lays out (160x130 and 150x140, with a small image in the same

@@ -63,6 +63,8 @@ CASES = [
     ("C", [(40, 70), (1, 29), (29, 1)], (16, 24), 4),  # h = 2, single rows and columns
     ("C", [(40, 70), (12, 11)], (7, 2), 1),          # lanes narrower than h + 1
     ("A", [(200, 9), (5, 300)], None, 2),            # tall and wide whole images
+    ("B", [(40, 70), (33, 17), (86, 64)], (86, 64), 16),  # a stream per row of a group
+    ("C", [(40, 70), (1, 29), (29, 1)], (16, 24), 8),    # rows p and p + 8 share a stream
 ]
 
 

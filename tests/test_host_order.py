@@ -4,12 +4,13 @@ The wavefront decoder (Sec. 3, Algorithm 1) pops a lane's symbols in this
 order: steps t ascending; the active rows of a step cut into groups of 16
 consecutive rows; per group the channels R, G, B; per channel the rows
 ascending, dealt to K interleaved rANS streams (row ts + r of a group goes
-to stream r mod K, K rows popped per round). Each stream's encoder walks its
-own symbols backwards (RevOrder in nx_order.hpp, compiled here for the
-host). The test restates the decoder's loop and checks, for every stream,
-that the encoder's walk is exactly its reverse, and that the streams
-together cover every symbol of the lane once, for lanes narrower than h + 1
-columns, single rows and columns, and ragged group sizes.
+to stream r mod K, K rows popped per round). The test restates the
+decoder's loop, checks that the streams together cover every symbol of the
+lane once, and that the encoder's layout (stream_rows_at, coding_slot in
+nx_order.hpp, compiled here for the host) puts every symbol at its index in
+its stream's coding order, the decode order reversed; for K = 1, 2, 4, 8,
+16, lanes narrower than h + 1 columns, single rows and columns, and ragged
+group sizes.
 """
 import os
 import subprocess
@@ -49,27 +50,15 @@ static std::vector<std::vector<Sym>> decoder_order(int Hl, int Wl, int h, int K)
 int main() {
   int cases = 0, bad = 0;
   for (int h = 1; h <= 3; ++h)
-    for (int K : {1, 2, 4})
-      for (int Hl = 1; Hl <= 70; Hl += (Hl < 6 ? 1 : 11))
+    for (int K : {1, 2, 4, 8, 16})
+      for (int Hl = 1; Hl <= 90; Hl += (Hl < 6 ? 1 : 13))
         for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13)) {
           ++cases;
+          const int o = h + 1, T = Wl + o * (Hl - 1);
           const auto dec = decoder_order(Hl, Wl, h, K);
+          // every symbol of the lane in exactly one stream
           std::vector<Sym> all;
-          for (int k = 0; k < K; ++k) {
-            RevOrder it;
-            it.init(Hl, Wl, h + 1, 0, K, k);
-            std::vector<Sym> enc;
-            while (!it.done && enc.size() <= (size_t)Hl * Wl * 3) {
-              enc.push_back(Sym(it.i, it.col(), it.c));
-              it.advance();
-            }
-            std::reverse(enc.begin(), enc.end());
-            if (enc != dec[k]) {
-              if (bad < 5) printf("order mismatch h=%d K=%d %dx%d stream %d\n", h, K, Hl, Wl, k);
-              ++bad;
-            }
-            all.insert(all.end(), enc.begin(), enc.end());
-          }
+          for (int k = 0; k < K; ++k) all.insert(all.end(), dec[k].begin(), dec[k].end());
           std::sort(all.begin(), all.end());
           bool cover = all.size() == (size_t)Hl * Wl * 3;
           for (size_t n = 0; cover && n < all.size(); ++n) {
@@ -80,97 +69,37 @@ int main() {
             if (bad < 5) printf("coverage h=%d K=%d %dx%d\n", h, K, Hl, Wl);
             ++bad;
           }
-        }
-  // raster: one stream, rows, columns, channels, backwards
-  for (int Hl = 1; Hl <= 9; ++Hl)
-    for (int Wl = 1; Wl <= 9; ++Wl) {
-      ++cases;
-      RevOrder it;
-      it.init(Hl, Wl, 4, 1, 1, 0);
-      int n = Hl * Wl * 3;
-      while (!it.done) {
-        --n;
-        if (Sym(it.i, it.col(), it.c) != Sym(n / (3 * Wl), n / 3 % Wl, n % 3)) ++bad;
-        it.advance();
-      }
-      if (n != 0) ++bad;
-    }
-  printf("%d cases %d bad\n", cases, bad);
-  return bad != 0;
-}
-"""
-
-
-def test_encoder_walk_reverses_decoder_order(tmp_path):
-    src = tmp_path / "order.cpp"
-    exe = tmp_path / "order"
-    src.write_text(DRIVER)
-    cmd = ["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I", "/opt/rocm/include",
-           str(src), "-o", str(exe)]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        pytest.fail("host build of nx_order.hpp failed:\n" + r.stderr[-2000:])
-    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
-    assert r.returncode == 0, r.stdout
-    assert " 0 bad" in r.stdout
-
-
-SLOT_DRIVER = r"""
-#include <cstdio>
-#include <vector>
-#include <tuple>
-#include "nx_order.hpp"
-using namespace nx;
-typedef std::tuple<int, int, int> Sym;
-
-int main() {
-  int cases = 0, bad = 0;
-  for (int h = 1; h <= 3; ++h)
-    for (int K : {1, 2, 4})
-      for (int Hl = 1; Hl <= 90; Hl += (Hl < 6 ? 1 : 13))
-        for (int Wl = 1; Wl <= 70; Wl += (Wl < 8 ? 1 : 13)) {
-          ++cases;
-          const int o = h + 1, T = Wl + o * (Hl - 1);
-          // the encoder's walk of every stream, and each stream's symbols after each step
-          std::vector<std::vector<Sym>> walk(K);
+          // coding order = decode order reversed; per step the stream's
+          // symbols of later steps from stream_rows_at
           std::vector<std::vector<long>> after(K, std::vector<long>(T, 0));
           for (int kk = 0; kk < K; ++kk) {
-            RevOrder it;
-            it.init(Hl, Wl, o, 0, K, kk);
-            while (!it.done) { walk[kk].push_back(Sym(it.i, it.col(), it.c)); it.advance(); }
             long S = 0;
             for (int t = T - 1; t >= 0; --t) { after[kk][t] = S; S += 3 * stream_rows_at(t, Hl, Wl, o, K, kk); }
-            if (S != (long)walk[kk].size()) { ++bad; if (bad < 5) printf("length h%d K%d %dx%d kk%d\n", h, K, Hl, Wl, kk); }
+            if (S != (long)dec[kk].size()) { ++bad; if (bad < 5) printf("length h%d K%d %dx%d kk%d\n", h, K, Hl, Wl, kk); }
           }
-          // every symbol's place from coding_slot is its index in its stream's walk
           for (int i = 0; i < Hl; ++i)
             for (int j = 0; j < Wl; ++j)
               for (int c = 0; c < 3; ++c) {
                 int kk, t, off;
                 coding_slot(i, j, c, Hl, Wl, o, K, kk, t, off);
                 const long p = after[kk][t] + off;
-                if (kk < 0 || kk >= K || p < 0 || p >= (long)walk[kk].size() || walk[kk][p] != Sym(i, j, c)) {
+                const long n = (long)dec[kk].size();
+                if (kk < 0 || kk >= K || p < 0 || p >= n || dec[kk][n - 1 - p] != Sym(i, j, c)) {
                   ++bad;
                   if (bad < 5) printf("slot h%d K%d %dx%d (%d,%d,%d)\n", h, K, Hl, Wl, i, j, c);
                 }
               }
         }
-  printf("%d cases, %d bad\n", cases, bad);
+  printf("%d cases %d bad\n", cases, bad);
   return bad != 0;
 }
 """
 
 
-def test_coding_slots_match_the_walk(tmp_path):
-    """The encoder lays each stream's symbols out in coding order from pixel
-    order: every symbol's place, coding_slot's offset within its step plus
-    the stream's symbols of later steps (from stream_rows_at), is its index
-    in the stream's reverse walk (RevOrder), and the per-step counts add up
-    to each stream's length; for lanes narrower than h + 1 columns, single
-    rows and columns, and ragged group sizes."""
-    src = tmp_path / "slot.cpp"
-    exe = tmp_path / "slot"
-    src.write_text(SLOT_DRIVER)
+def build_and_run(tmp_path, driver, name):
+    src = tmp_path / f"{name}.cpp"
+    exe = tmp_path / name
+    src.write_text(driver)
     cmd = ["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I", CSRC, "-I", "/opt/rocm/include",
            str(src), "-o", str(exe)]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -179,3 +108,7 @@ def test_coding_slots_match_the_walk(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout
     assert " 0 bad" in r.stdout
+
+
+def test_streams_cover_the_lane_and_slots_reverse_the_decode_order(tmp_path):
+    build_and_run(tmp_path, DRIVER, "order")
