@@ -5,8 +5,9 @@ Workload (synthetic, seeded): 4 images of 1024x1024 and 2 of 2048x1536 uint8
 RGB (smooth random fields, sigma 4 px, 20 step edges, +-3 integer noise),
 coded with the h=3, 64-channel, 2-block local model (random-init weights) in
 the wavefront order with independent patches of 64 columns, each patch one
-lane of 4 interleaved rANS streams; the patch height is the shortest that
-keeps the batch at two lanes per SIMD (86 rows on 256 CUs: 1,920 lanes). One timed step = one decode
+lane of 16 interleaved rANS streams (one per row of a 16-row group); the
+patch height is the shortest that keeps the batch at two lanes per SIMD (86
+rows on 256 CUs: 1,920 lanes). One timed step = one decode
 of the whole batch from containers already resident in HBM, by default in the
 sheared layout (ShearLoC, Sec. 3.1 and Algorithm 2); the unsheared wavefront
 decoder (Algorithm 1) is timed on the same containers as a second leg.
@@ -34,10 +35,8 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # 256 MiB device copy, per decoder layout; valid only for the kernel sources,
 # patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "sheared": {"src_sha": "b35992e3b57d4f18", "patch": (86, 64), "interleave": 4,
-                "fetch_kib": 27520.8, "write_kib": 555196.7, "fetch_scale": 1.99981, "write_scale": 1.0},
-    "unsheared": {"src_sha": "b35992e3b57d4f18", "patch": (86, 64), "interleave": 4,
-                  "fetch_kib": 38416.2, "write_kib": 32044.4, "fetch_scale": 1.99981, "write_scale": 1.0},
+    "sheared": {"src_sha": "9d68b0c951b6a340", "patch": (86, 64), "interleave": 16,
+                "fetch_kib": 34754.5, "write_kib": 736096.8, "fetch_scale": 1.99982, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
@@ -53,8 +52,8 @@ def kernel_sources_sha() -> str:
 
 
 def decode_traffic_bytes(layout: str, patch, interleave: int):
-    t = DECODE_TRAFFIC[layout]
-    if kernel_sources_sha() != t["src_sha"] or tuple(patch) != t["patch"] or interleave != t["interleave"]:
+    t = DECODE_TRAFFIC.get(layout)
+    if t is None or kernel_sources_sha() != t["src_sha"] or tuple(patch) != t["patch"] or interleave != t["interleave"]:
         return None
     return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 
@@ -69,6 +68,53 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------- oracle pool
+# The CPU baseline runs the oracle (FP64 C, one lane per call) in worker
+# processes, one per core of the box's share; each worker loads the model once.
+_ORACLE = None
+
+
+def _oracle_init(blob: bytes) -> None:
+    global _ORACLE
+    sys.path.insert(0, ROOT)
+    import oracle
+
+    _ORACLE = oracle.Model.from_blob(blob)
+
+
+def _oracle_job(job):
+    """('enc', lane) -> container; ('dec', lane, container) -> None (checked
+    exact); ('stats', lane) -> quantised ideal bits."""
+    import numpy as np
+
+    kind, lane = job[0], job[1]
+    if kind == "enc":
+        return _ORACLE.encode(lane, 1)
+    if kind == "dec":
+        out = _ORACLE.decode(job[2], lane.shape[0], lane.shape[1], 1)
+        assert np.array_equal(out, lane), "oracle round trip failed"
+        return None
+    return _ORACLE.stats(lane)["qbits"]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cpus() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,19 +123,21 @@ def main():
     ap.add_argument("--patch", default="auto",
                     help="patch shape ROWSxCOLS, one number for square patches, or auto: the shortest 64-column "
                          "patch that keeps the batch at two lanes per SIMD (tune.balanced_patch)")
-    ap.add_argument("--interleave", type=int, default=4, help="rANS streams per lane (1, 2 or 4)")
+    ap.add_argument("--interleave", type=int, default=16, help="rANS streams per lane (1, 2, 4, 8 or 16)")
     ap.add_argument("--layout", choices=("sheared", "unsheared"), default="sheared",
                     help="decoder layout of the headline decode: sheared (ShearLoC, Algorithm 2) or the "
                          "unsheared wavefront decoder (Algorithm 1); the other is timed as a second leg")
     ap.add_argument("--raster-rows", type=int, default=32,
                     help="rows of the 1024-wide strip the raster baseline decodes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-lanes", type=int, default=32, help="lanes of image 0 the oracle decodes")
+    ap.add_argument("--cpu-lanes", type=int, default=32, help="lanes of image 0 the oracle decodes on one thread")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="oracle processes of the all-cores leg (at most the CPUs this process may use)")
     ap.add_argument("--train-steps", type=int, default=50,
                     help="timed training steps (model B, 64 random 32x32 crops, Adam); 0 skips the leg")
     ap.add_argument("--no-trained", action="store_true",
-                    help="skip the trained-model leg (model B after the 2000-step training recipe: decode time "
-                         "and the bits gap at about 3 bits/dim)")
+                    help="skip the trained-model leg (model B after the 2000-step training recipe, trained on the "
+                         "CPU by the oracle: decode time and the bits gap at about 4 bits/dim)")
     ap.add_argument("--profile", action="store_true",
                     help="time only the batch decode, then run the full-image pass and the encode three times "
                          "each and a known-size copy for counter calibration (for profiler runs; prints no "
@@ -407,35 +455,49 @@ def main():
     gap = None
     cpu = None
     if not args.no_cpu:
+        import multiprocessing as mp
+
         import oracle
 
-        om = oracle.Model.from_blob(blob)
         c0 = cont[offs_h[0]:offs_h[1]]
         nl0 = int.from_bytes(bytes(c0[28:32]), "little")
         K0 = int(c0[7])
         ends = np.frombuffer(bytes(c0[32:32 + 4 * nl0 * K0]), dtype="<u4").astype(np.int64)
         # bits per lane: the sum of its K stream payloads
         lane_bits = np.diff(np.concatenate([[0], ends])).reshape(nl0, K0).sum(axis=1) * 8
-        sample = [0, lanes_x + 3, nl0 - 1]
-        ideal = got = 0.0
-        for q in sample:
-            ideal += om.stats(lane_crop(imgs[0], q))["qbits"]
-            got += float(lane_bits[q])
+        crops = [lane_crop(imgs[0], q) for q in range(nl0)]
+        procs = max(1, min(args.cpu_procs, usable_cpus()))
+        with mp.get_context("spawn").Pool(procs, initializer=_oracle_init, initargs=(blob,)) as pool:
+            pool.map(_oracle_job, [("stats", crops[0][:4, :4].copy())] * procs)  # workers up and loaded
+            t0 = time.time()
+            encs = pool.map(_oracle_job, [("enc", c) for c in crops], chunksize=1)
+            enc_s = time.time() - t0
+            t0 = time.time()
+            pool.map(_oracle_job, [("dec", c, e) for c, e in zip(crops, encs)], chunksize=1)
+            dec_s = time.time() - t0
+            ideals = pool.map(_oracle_job, [("stats", c) for c in crops], chunksize=1)
+        # the gap over every lane of image 0
+        ideal, got = float(sum(ideals)), float(lane_bits.sum())
         gap = (got - ideal) / ideal
-        log(f"[bench] gap on {len(sample)} lanes: {gap * 100:.4f}% ({got:.0f} vs {ideal:.1f} bits)")
-        # oracle CPU decode rate on a bounded sample of the same workload
-        crops = [lane_crop(imgs[0], q) for q in range(args.cpu_lanes)]
-        encs = [om.encode(c, 1) for c in crops]
-        c0t = time.time()
-        for c, enc in zip(crops, encs):
+        log(f"[bench] gap on all {nl0} lanes of image 0: {gap * 100:.4f}% ({got:.0f} vs {ideal:.1f} bits, "
+            f"{(got - ideal) / (nl0 * K0):.1f} bits per stream)")
+        # one thread: the oracle in this process on the first lanes
+        om = oracle.Model.from_blob(blob)
+        c1 = time.time()
+        for c, enc in zip(crops[:args.cpu_lanes], encs):
             dec = om.decode(enc, c.shape[0], c.shape[1], 1)
             assert np.array_equal(dec, c)
-        cpu_s = time.time() - c0t
-        cpu = {"value": sum(c.shape[0] * c.shape[1] for c in crops) / cpu_s, "unit": "decoded px/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_lanes} {pname} lanes of image 0, wavefront order, "
-                         f"FP64 C oracle, 1 thread, {cpu_s:.1f}s"}
-        log(f"[bench] oracle CPU: {cpu['value']:.1f} px/s")
+        one_s = time.time() - c1
+        lpx = sum(c.shape[0] * c.shape[1] for c in crops)
+        one_px = sum(c.shape[0] * c.shape[1] for c in crops[:args.cpu_lanes])
+        cpu = {"value": lpx / dec_s, "unit": "decoded px/s", "cores": procs, "kind": "oracle",
+               "encode_px_per_s": lpx / enc_s, "decode_px_per_s_1thread": one_px / one_s,
+               "nproc": os.cpu_count(), "usable_cpus": usable_cpus(), "cpu_model": cpu_model(),
+               "sample": f"all {nl0} {pname} lanes of image 0 (1024x1024, {lpx} px), wavefront order, FP64 C "
+                         f"oracle, one lane per call in {procs} processes: encode {enc_s:.1f} s, decode "
+                         f"{dec_s:.1f} s; one thread: {args.cpu_lanes} lanes decoded in {one_s:.1f} s"}
+        log(f"[bench] oracle CPU ({procs} processes, {cpu['cpu_model']}): decode {cpu['value']:.0f} px/s, encode "
+            f"{cpu['encode_px_per_s']:.0f} px/s; one thread decode {cpu['decode_px_per_s_1thread']:.0f} px/s")
 
     # training leg: one step = forward + hand-written backward + Adam on
     # 64 random 32x32 crops, model B
@@ -474,21 +536,15 @@ def main():
                      "sample": "model B, 64 random 32x32 crops per step, forward + backward + Adam"}
         log(f"[bench] training step {tstep * 1e3:.3f} ms ({tflops / 1e12:.1f} TFLOP/s fwd+bwd)")
 
-    # the same workload coded by a trained model B (the 2000-step training
-    # recipe, ~3 bits/dim): decode time and, on the oracle's sampled lanes,
-    # the gap with the configured streams and with one stream
+    # the same workload coded by the trained model B (the 2000-step training
+    # recipe, run on the CPU by the oracle; ~4.4 bits/dim here): decode time
+    # and, over every lane of image 0, the gap with the configured streams and
+    # with one stream
     trained_rec = None
     if not args.no_trained:
-        from paper_2201_05213_amd import blob as nxblob, train as nxtrain
-
-        tdims, tparams = nxblob.params_from_blob(blob)
-        tpool = torch.from_numpy(synth.training_pool(n=512)).to(dev)
-        t0 = time.time()
-        tp = nxtrain.fit(torch.from_numpy(tparams).to(dev), tdims, tpool, 2000,
-                         np.random.Generator(np.random.PCG64(5_999_999)))
-        torch.cuda.synchronize()
-        fit_s = time.time() - t0
-        mt = nx.Model(nxblob.blob_from_params(tdims, tp.cpu().numpy()))
+        with open(os.path.join(ROOT, "tests", "golden", "model_b_trained.nlxw"), "rb") as f:
+            tblob = f.read()
+        mt = nx.Model(tblob)
         td, to = mt.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=args.interleave)
         plan3, ws3 = mt.decode_prepare(outs, order=dec_order, patch=patch, interleave=args.interleave)
         mt.decode_run(plan3, td, to, status, ws3)
@@ -508,29 +564,57 @@ def main():
             c = tc[toh[k]:toh[k + 1]]
             nl = int.from_bytes(bytes(c[28:32]), "little")
             tbits += 8 * (len(c) - 32 - 4 * nl * int(c[7]))
-        trained_rec = {"train_s": fit_s, "bits_per_dim": tbits / (3 * npx), "decode_ms": t_step * 1e3,
-                       "px_per_s": npx / t_step}
-        log(f"[bench] trained model B ({fit_s:.1f}s to train): {tbits / (3 * npx):.3f} bits/dim, decode "
-            f"{t_step * 1e3:.2f} ms ({npx / t_step / 1e6:.0f} Mpx/s)")
+        trained_rec = {"bits_per_dim": tbits / (3 * npx), "decode_ms": t_step * 1e3, "px_per_s": npx / t_step,
+                       "model": "model B after 2000 Adam steps (tests/golden/model_b_trained.nlxw)"}
+        log(f"[bench] trained model B: {tbits / (3 * npx):.3f} bits/dim, decode {t_step * 1e3:.2f} ms "
+            f"({npx / t_step / 1e6:.0f} Mpx/s)")
         del ws3
         if not args.no_cpu:
-            import oracle
+            import multiprocessing as mp
 
-            tom = oracle.Model.from_blob(nxblob.blob_from_params(tdims, tp.cpu().numpy()))
-            sample = [0, lanes_x + 3, lanes_x * -(-1024 // ph) - 1]
-            crops = [lane_crop(imgs[0], q) for q in sample]
-            ideal = sum(tom.stats(c)["qbits"] for c in crops)
+            crops = [lane_crop(imgs[0], q) for q in range(lanes_x * -(-1024 // ph))]
+            procs = max(1, min(args.cpu_procs, usable_cpus()))
+            with mp.get_context("spawn").Pool(procs, initializer=_oracle_init, initargs=(tblob,)) as pool:
+                ideal = float(sum(pool.map(_oracle_job, [("stats", c) for c in crops], chunksize=1)))
             for K in sorted({args.interleave, 1}):
                 dK, oK = mt.encode([ts[0]], order=nx.WAVEFRONT, patch=patch, interleave=K)
                 c0 = dK.cpu().numpy()
                 nl0 = int.from_bytes(bytes(c0[28:32]), "little")
-                ends = np.frombuffer(bytes(c0[32:32 + 4 * nl0 * K]), dtype="<u4").astype(np.int64)
-                lb = np.diff(np.concatenate([[0], ends])).reshape(nl0, K).sum(axis=1) * 8
-                got = float(sum(lb[q] for q in sample))
+                got = 8.0 * (len(c0) - 32 - 4 * nl0 * K)
                 trained_rec[f"gap_vs_oracle_ideal_k{K}"] = (got - ideal) / ideal
-                log(f"[bench] trained model B, {K} stream(s): gap on {len(sample)} lanes "
-                    f"{100 * (got - ideal) / ideal:.4f}% ({(got - ideal) / len(sample):.1f} bits per lane)")
-            trained_rec["gap_sample"] = f"lanes {sample} of image 0, {pname} patches"
+                log(f"[bench] trained model B, {K} stream(s): gap on all {nl0} lanes of image 0 "
+                    f"{100 * (got - ideal) / ideal:.4f}% ({(got - ideal) / (nl0 * K):.1f} bits per stream)")
+            trained_rec["gap_sample"] = f"all {len(crops)} {pname} lanes of image 0"
+
+    # what the patches cost in bits: the quantised ideal code length (the
+    # encoder's own CDFs, every pixel) of whole-image lanes against patches,
+    # per workload and model; beside it the oracle's FP64 figures for the
+    # same layouts if tests/golden/patch_cost.json holds them
+    patch_cost = {}
+    models_pc = {"B": m}
+    tpath = os.path.join(ROOT, "tests", "golden", "model_b_trained.nlxw")
+    if os.path.exists(tpath):
+        with open(tpath, "rb") as f:
+            models_pc["B_trained"] = nx.Model(f.read())
+    layouts = {"whole": None, f"{ph}x{pw}": patch, "64x64": (64, 64), "32x32": (32, 32)}
+    wl = {"large6": ts, "uneven64": [torch.from_numpy(i).to(dev) for i in synth.workload_images("uneven64")]}
+    for mname, mm in models_pc.items():
+        for wname, wts in wl.items():
+            wpx = sum(int(t.shape[0]) * int(t.shape[1]) for t in wts)
+            rec = {}
+            for lname, lp in layouts.items():
+                _, ideal_img = mm.debug_symbols(wts, patch=lp)
+                rec[lname] = {"qbits_per_dim": float(ideal_img.sum()) / (3 * wpx)}
+            for lname in rec:
+                rec[lname]["cost_vs_whole"] = rec[lname]["qbits_per_dim"] / rec["whole"]["qbits_per_dim"] - 1.0
+            patch_cost.setdefault(mname, {})[wname] = rec
+            log(f"[bench] patch cost, model {mname}, {wname}: " + ", ".join(
+                f"{k} {v['qbits_per_dim']:.4f} ({100 * v['cost_vs_whole']:+.2f}%)" for k, v in rec.items()))
+    del wl
+    opath = os.path.join(ROOT, "tests", "golden", "patch_cost.json")
+    if os.path.exists(opath):
+        with open(opath) as f:
+            patch_cost["oracle"] = json.load(f)["results"]
 
     out = {
         "metric": "decoded pixels/sec on 1 GPU, wavefront+patch vs raster; bits/dim gap vs FP64 oracle",
@@ -578,6 +662,7 @@ def main():
         "cpu_baseline": cpu,
         "training": train_rec,
         "trained_model": trained_rec,
+        "patch_bpd_cost": patch_cost,
     }
     print(json.dumps(out))
 
