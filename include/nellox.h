@@ -20,7 +20,8 @@
  *   whose 16-bit reversal lies in the symbol's range, so it grows the state
  *   by about 2^16 / f; the final state is flushed as its significant bytes),
  *   one stream per lane or K = 2, 4, 8, 16 interleaved streams per lane (opts.interleave):
- *   in a wavefront step, row i - i_first goes to stream (i - i_first) mod K.
+ *   in a wavefront step, row i - i_first goes to stream (i - i_first) mod K;
+ *   or one stream per lane row (interleave -1), its pixels left to right.
  *   Decoding order (nellox_opts.order):
  *     0 raster: one pixel after the other (the sequential decoder of Sec. 2);
  *     1 wavefront: pixel (i,j) at step t = j + (h+1) i, all pixels of a step
@@ -79,7 +80,11 @@ typedef struct {
                          order only): the rows of every wavefront step are dealt to
                          the states in turn, so a decoder can search that many
                          symbols at once (with 16, every row of a 16-row group has
-                         its own stream); each extra state costs one stream's start
+                         its own stream); -1 (wavefront order 1 only): one stream
+                         per lane row, so every row of every step decodes at once,
+                         the lane in bands of 64 rows on as many CUs (meant for
+                         whole-image lanes, the paper's exact method: a row of W
+                         pixels costs one stream). Each stream costs its start
                          and flush, about 4.6 bits */
 } nellox_opts;
 
@@ -185,6 +190,8 @@ typedef struct {
   int64_t counter_offset;       /* byte offset of the lane-queue counter */
   int64_t ring_offset;          /* order 2: byte offset of the per-wave sheared context rings */
   int64_t ring_rows;            /* order 2: rows of a ring (tallest lane + h, padded) */
+  int64_t n_bands;              /* row streams: bands of 64 lane rows (the launch's work items) */
+  int64_t progress_offset;      /* row streams: byte offset of the per-band progress counters */
 } nellox_decode_plan;
 
 nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nellox_image* out,

@@ -17,7 +17,7 @@ import torch
 
 from ._lib import NelloxDecodePlan, NelloxError, NelloxImage, NelloxOpts, check, load
 
-__all__ = ["Model", "NelloxError", "load", "RASTER", "WAVEFRONT", "SHEARED"]
+__all__ = ["Model", "NelloxError", "load", "RASTER", "WAVEFRONT", "SHEARED", "ROWS"]
 
 RASTER = 0
 WAVEFRONT = 1
@@ -235,6 +235,19 @@ def debug_check_monotone(device=None) -> dict:
     return {"exp2_decreasing": c[0], "rcp_increasing": c[1], "sigmoid_increasing": c[2], "pairs": c[3]}
 
 
+ROWS = -1  # interleave: one rANS stream per lane row
+
+
+def container_streams(c: bytes) -> int:
+    """rANS streams (stream table entries) of a container, from its header:
+    lanes x K, or with row streams (stream byte 0) the lane rows, H per
+    column of patches."""
+    H, W = int.from_bytes(c[8:12], "little"), int.from_bytes(c[12:16], "little")
+    pw = int.from_bytes(c[18:20], "little") or W
+    nl = int.from_bytes(c[28:32], "little")
+    return nl * c[7] if c[7] else -(-W // pw) * H
+
+
 def payload_bits(data, offsets) -> list:
     """Coded bits per image: the stream payloads (final states and
     renormalisation bytes), without the header and the stream table."""
@@ -243,8 +256,7 @@ def payload_bits(data, offsets) -> list:
     out = []
     for k in range(len(o) - 1):
         c = d[o[k]:o[k + 1]]
-        nl = int.from_bytes(c[28:32], "little")
-        out.append(8 * (len(c) - 32 - 4 * nl * c[7]))
+        out.append(8 * (len(c) - 32 - 4 * container_streams(c)))
     return out
 
 

@@ -25,7 +25,8 @@ class NelloxDecodePlan(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("order", ctypes.c_int32), ("interleave", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_lanes", ctypes.c_int64),
                 ("model_hash", ctypes.c_uint64), ("ws_bytes", ctypes.c_int64), ("desc_offset", ctypes.c_int64),
-                ("counter_offset", ctypes.c_int64), ("ring_offset", ctypes.c_int64), ("ring_rows", ctypes.c_int64)]
+                ("counter_offset", ctypes.c_int64), ("ring_offset", ctypes.c_int64), ("ring_rows", ctypes.c_int64),
+                ("n_bands", ctypes.c_int64), ("progress_offset", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)

@@ -103,7 +103,8 @@ hipError_t stage_copy(nellox_model* m, void* dst, const void* src, size_t bytes,
 struct Plan {
   std::vector<ImgDesc> d;
   int64_t n_tiles = 0, n_lanes = 0, n_px = 0, slot_bytes = 0;
-  int K = 1;       // rANS streams per lane
+  int64_t n_streams = 0, n_bands = 0;  // rANS streams of the batch; row streams: decoding bands
+  int K = 1;       // rANS streams per lane (ROW_STREAMS: one per lane row)
   int order = 0;   // 0 raster, 1 wavefront, 2 wavefront decoded in the sheared layout
   int ph_max = 0;  // tallest lane of the batch
   int64_t ring_waves = 0, ring_rows = 0;  // sheared context rings (set by plan_ring)
@@ -122,9 +123,12 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
   if (o->order < 0 || o->order > 2)
     return fail(NELLOX_E_ARG, "order must be 0 (raster), 1 (wavefront) or 2 (wavefront, sheared layout)");
   P.order = o->order;
-  P.K = o->interleave <= 1 ? 1 : o->interleave;
-  if (!valid_interleave(P.K)) return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2, 4, 8 or 16");
-  if (P.K > 1 && o->order == 0) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
+  P.K = o->interleave == -1 ? ROW_STREAMS : o->interleave <= 1 ? 1 : o->interleave;
+  if (P.K != ROW_STREAMS && !valid_interleave(P.K))
+    return fail(NELLOX_E_ARG, "interleave must be 0, 1, 2, 4, 8, 16, or -1 (a stream per row)");
+  if (P.K != 1 && o->order == 0) return fail(NELLOX_E_ARG, "interleaved streams need the wavefront order");
+  if (P.K == ROW_STREAMS && o->order == 2)
+    return fail(NELLOX_E_ARG, "row streams are decoded in the wavefront order (1), not the sheared layout");
   P.d.resize(n);
   for (int k = 0; k < n; ++k) {
     const nellox_image& im = imgs[k];
@@ -150,11 +154,21 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
     P.n_px += npx;
     P.n_tiles += (int64_t)im.H * D.ntx;
     P.ph_max = std::max(P.ph_max, D.ph);
-    P.slot_bytes += P.K * (6 * npx + 8 * nl);
+    const int64_t ns = image_streams(P.K, im.H, D.nlx, D.nly);
+    D.stream_base = P.n_streams;
+    P.n_streams += ns;
     D.rev_base = P.rev_words;
     D.after_base = P.after_words;
-    P.rev_words += nl * P.K * stream_rev_words(D.ph, D.pw, P.K);
-    P.after_words += nl * P.K * stream_after_entries(D.ph, D.pw);
+    if (P.K == ROW_STREAMS) {
+      // a slot of 6 B per pixel and 8 B per row stream; the symbols are read in place
+      P.slot_bytes += 6 * npx + 8 * ns;
+      D.band_base = P.n_bands;
+      P.n_bands += image_bands(im.H, D.ph, D.nlx, D.nly);
+    } else {
+      P.slot_bytes += P.K * (6 * npx + 8 * nl);
+      P.rev_words += nl * P.K * stream_rev_words(D.ph, D.pw, P.K);
+      P.after_words += nl * P.K * stream_after_entries(D.ph, D.pw);
+    }
     P.max_lane_px = std::max(P.max_lane_px, (int64_t)D.ph * D.pw);
   }
   return NELLOX_OK;
@@ -162,10 +176,11 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
 
 // Workspace segments: first those of decoding, sampling, the NLL and the
 // debug calls (descriptors, queue counter, sheared windows, per-pixel bits,
-// partial sums; `small` bytes), then the encoder's alone (per-image sizes,
-// stream lengths, symbols, stream slots, coding-order buffers).
+// partial sums, row-stream band progress; `small` bytes), then the
+// encoder's alone (per-image sizes, stream lengths, symbols, stream slots,
+// coding-order buffers).
 struct WsLayout {
-  int64_t desc, flags, ring, bits, partials, small;
+  int64_t desc, flags, ring, bits, partials, progress, small;
   int64_t img_bytes, lane_len, lane_end, sym, slots, rev, after, total;
 };
 
@@ -177,10 +192,11 @@ WsLayout ws_layout(const Plan& P, int n) {
   W.ring = o; o = align256(o + P.ring_waves * ring_wave_bytes(P.ring_rows));
   W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
   W.partials = o; o = align256(o + 8LL * REDUCE_PARTS * std::max(n, 1));
+  W.progress = o; o = align256(o + 4 * std::max<int64_t>(P.n_bands, 1));
   W.small = o;
   W.img_bytes = o; o = align256(o + 8LL * std::max(n, 1));
-  W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
-  W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_lanes * P.K, 1));
+  W.lane_len = o; o = align256(o + 4 * std::max<int64_t>(P.n_streams, 1));
+  W.lane_end = o; o = align256(o + 4 * std::max<int64_t>(P.n_streams, 1));
   W.sym = o; o = align256(o + 12 * std::max<int64_t>(P.n_px, 1));
   W.slots = o; o = align256(o + std::max<int64_t>(P.slot_bytes, 1));
   W.rev = o; o = align256(o + 4 * std::max<int64_t>(P.rev_words, 1));
@@ -433,11 +449,12 @@ size_t nellox_encode_bound(int32_t H, int32_t W, const nellox_opts* o) {
   if (H < 1 || W < 1) return 0;
   const int ph = (!o || o->patch_h <= 0 || o->patch_h > H) ? H : o->patch_h;
   const int pw = (!o || o->patch_w <= 0 || o->patch_w > W) ? W : o->patch_w;
-  const int64_t K = (!o || o->interleave <= 1) ? 1 : o->interleave;
-  if (!valid_interleave((int)K)) return 0;
-  const int64_t nl = (int64_t)((H + ph - 1) / ph) * ((W + pw - 1) / pw);
+  const int64_t K = !o ? 1 : o->interleave == -1 ? ROW_STREAMS : o->interleave <= 1 ? 1 : o->interleave;
+  if (K != ROW_STREAMS && !valid_interleave((int)K)) return 0;
+  const int nlx = (W + pw - 1) / pw, nly = (H + ph - 1) / ph;
+  const int64_t ns = image_streams((int)K, H, nlx, nly);
   // header, stream table, per stream at most 4 flush bytes, at most 2 bytes per symbol
-  return (size_t)(HDR_BYTES + 4 * nl * K + 4 * nl * K + 6LL * H * W);
+  return (size_t)(HDR_BYTES + 4 * ns + 4 * ns + 6LL * H * W);
 }
 
 size_t nellox_workspace_bytes(const nellox_model* m, int32_t n, const nellox_image* imgs, const nellox_opts* o) {
@@ -479,6 +496,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   r.desc = (const ImgDesc*)(w8 + W.desc);
   r.n_img = n;
   r.n_lanes = P.n_lanes;
+  r.n_streams = P.n_streams;
   r.order = coded_order(o->order);
   r.h = m->h;
   r.K = P.K;
@@ -494,6 +512,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
   pk.desc = r.desc;
   pk.n_img = n;
   pk.n_lanes = P.n_lanes;
+  pk.n_streams = P.n_streams;
   pk.order = coded_order(o->order);
   pk.h = m->h;
   pk.K = P.K;
@@ -515,7 +534,7 @@ nellox_status nellox_encode(const nellox_model* mc, int32_t n, const nellox_imag
 
 nellox_status nellox_peek(const uint8_t* c, size_t len, int32_t* H, int32_t* W, nellox_opts* o) {
   if (!c) return fail(NELLOX_E_ARG, "container is null");
-  if (len < (size_t)HDR_BYTES || memcmp(c, "NLXC", 4) != 0 || c[4] != CONTAINER_VERSION || !valid_interleave(c[7]))
+  if (len < (size_t)HDR_BYTES || memcmp(c, "NLXC", 4) != 0 || c[4] != CONTAINER_VERSION || !valid_stream_code(c[7]))
     return fail(NELLOX_E_CORRUPT, "not a container of this version");
   const int32_t h = (int32_t)rd32(c + 8), w = (int32_t)rd32(c + 12);
   if (H) *H = h;
@@ -524,7 +543,7 @@ nellox_status nellox_peek(const uint8_t* c, size_t len, int32_t* H, int32_t* W, 
     o->order = c[5];
     o->patch_h = c[16] | (c[17] << 8);
     o->patch_w = c[18] | (c[19] << 8);
-    o->interleave = c[7];
+    o->interleave = c[7] == ROW_STREAMS ? -1 : c[7];
   }
   return NELLOX_OK;
 }
@@ -543,11 +562,19 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && (st = upload_plan(m, P, (uint8_t*)ws, W, s))) return st;
   int grid = 0, waves = 0;
-  decode_shape(P.n_lanes, persistent_grid(m), grid, waves);
+  if (P.K == ROW_STREAMS) {
+    // row streams: a workgroup per band, every band of the batch in flight if the CUs allow
+    waves = ROW_WAVES;
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(persistent_grid(m), P.n_bands));
+  } else {
+    decode_shape(P.n_lanes, persistent_grid(m), grid, waves);
+  }
   memset(plan, 0, sizeof(*plan));
   plan->n = n;
   plan->order = o->order;
-  plan->interleave = P.K;
+  plan->interleave = P.K == ROW_STREAMS ? -1 : P.K;
+  plan->n_bands = P.n_bands;
+  plan->progress_offset = W.progress;
   plan->waves = std::max(waves, 1);
   plan->grid = grid;
   plan->ring_offset = W.ring;
@@ -565,8 +592,11 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
 static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, const uint8_t* in,
                               const uint64_t* in_offsets, int32_t* status, uint32_t* dump, void* ws, void* stream) {
   if (check_model(m)) return NELLOX_E_ARG;
+  const bool rows = plan && plan->interleave == -1;
   if (!plan || plan->model_hash != m->hash || plan->n < 0 || plan->waves < 1 || plan->waves > DECODE_WAVES ||
-      !valid_interleave(plan->interleave) || plan->order < 0 || plan->order > 2 ||
+      (!rows && !valid_interleave(plan->interleave)) || plan->order < 0 || plan->order > 2 ||
+      (rows && (plan->order != 1 || plan->waves != ROW_WAVES || plan->n_bands < 0 ||
+                plan->progress_offset + 4 * plan->n_bands > plan->ws_bytes)) ||
       (plan->order == 2 && plan->n_lanes > 0 &&
        (ring_windows(plan->grid, plan->waves) * ring_wave_bytes(plan->ring_rows) > plan->ws_bytes ||
         plan->ring_rows < 4)))
@@ -577,7 +607,8 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
   int32_t* counter = (int32_t*)(w8 + plan->counter_offset);
-  hipError_t e = launch_decode_prep(status, n, counter, s);
+  int32_t* progress = rows ? (int32_t*)(w8 + plan->progress_offset) : nullptr;
+  hipError_t e = launch_decode_prep(status, n, counter, s, progress, rows ? plan->n_bands : 0);
   if (e != hipSuccess) return hip_fail(e, "decode prep launch");
   DecArgs a{};
   a.w = m->dw;
@@ -596,7 +627,14 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   a.sym_dump = dump;
   a.ring = plan->order == 2 ? w8 + plan->ring_offset : nullptr;
   a.ring_rows = (int)plan->ring_rows;
-  e = launch_decode(m->h, m->Cp, a, plan->grid, plan->waves, s);
+  a.progress = progress;
+  a.n_bands = plan->n_bands;
+  if (rows) {
+    a.K = ROW_STREAMS;
+    e = launch_decode_rows(m->h, m->Cp, a, plan->grid, s);
+  } else {
+    e = launch_decode(m->h, m->Cp, a, plan->grid, plan->waves, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "decoder launch");
   return NELLOX_OK;
 }

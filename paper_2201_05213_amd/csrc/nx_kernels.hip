@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "nx_device.hpp"
@@ -34,6 +35,56 @@ NXD int find_img(const ImgDesc* __restrict__ d, int n, int64_t key, bool by_lane
     if (b <= key) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// the image holding global stream `key` (by its first stream)
+NXD int find_img_stream(const ImgDesc* __restrict__ d, int n, int64_t key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].stream_base <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Where stream e of an image (its stream table entry) lies: its lane (q, and
+// the patch row and column ly, lx), the lane's rows and columns, its index
+// among the lane's streams (kk, K streams) or its row (r, row streams), the
+// pixels of the lanes before it in lane order, and the end of its byte slot
+// in the encoder's slot buffer (slots are laid out in entry order: with K
+// streams, K slots of 6 B per lane pixel + 8 B per lane; with row streams,
+// 6 B per row pixel + 8 B per row).
+struct StreamAt {
+  int q, ly, lx, Hl, Wl, kk, r;
+  int64_t lane_px_off, slot_end;
+};
+NXD StreamAt stream_at(const ImgDesc& D, int K, int64_t e) {
+  StreamAt S;
+  if (K == ROW_STREAMS) {
+    const int64_t per_prow = (int64_t)D.nlx * D.ph;  // entries of a full patch row
+    S.ly = (int)(e / per_prow);
+    S.Hl = min(D.ph, D.H - S.ly * D.ph);
+    const int64_t rem = e - (int64_t)S.ly * per_prow;
+    S.lx = (int)(rem / S.Hl);
+    S.r = (int)(rem - (int64_t)S.lx * S.Hl);
+    S.kk = 0;
+  } else {
+    const int q = (int)(e / K);
+    S.kk = (int)(e - (int64_t)q * K);
+    S.ly = q / D.nlx;
+    S.lx = q - S.ly * D.nlx;
+    S.Hl = min(D.ph, D.H - S.ly * D.ph);
+    S.r = 0;
+  }
+  S.q = S.ly * D.nlx + S.lx;
+  S.Wl = min(D.pw, D.W - S.lx * D.pw);
+  S.lane_px_off = (int64_t)S.ly * D.ph * D.W + (int64_t)S.lx * D.pw * S.Hl;
+  if (K == ROW_STREAMS)
+    S.slot_end = D.slot_base + 6 * (S.lane_px_off + (int64_t)(S.r + 1) * S.Wl) + 8 * (e + 1);
+  else
+    S.slot_end = D.slot_base + K * (6 * S.lane_px_off + 8 * (int64_t)S.q) +
+                 (S.kk + 1) * lane_slot_bytes((int64_t)S.Hl * S.Wl);
+  return S;
 }
 
 
@@ -345,7 +396,7 @@ __device__ __forceinline__ void rans_put(uint32_t& x, uint8_t*& out, const uint3
 // one thread per stream (lane L, stream k): stream index L K + k
 __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
   const int64_t SL = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (SL >= A.n_lanes * A.K) return;
+  if (SL >= A.n_streams) return;
   const StreamGeom G = stream_geom(A, SL);
   const int64_t slot_end = G.D.slot_base + A.K * (6 * G.lane_px_off + 8 * (int64_t)G.q) +
                            (G.kk + 1) * lane_slot_bytes((int64_t)G.Hl * G.Wl);
@@ -382,6 +433,35 @@ __global__ void __launch_bounds__(64) k_rans_enc(RansEncArgs A) {
   A.lane_len[SL] = (uint32_t)((A.slots + slot_end) - out);
 }
 
+// Row streams: one thread per stream (a lane row). Its symbols in decode
+// order are the row's pixels left to right, R, G, B, so in coding order they
+// are read in place from the symbol buffer, backwards.
+__global__ void __launch_bounds__(64) k_rans_enc_rows(RansEncArgs A) {
+  const int64_t SL = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (SL >= A.n_streams) return;
+  const int n = find_img_stream(A.desc, A.n_img, SL);
+  const ImgDesc D = A.desc[n];
+  const int64_t e = SL - D.stream_base;
+  const StreamAt S = stream_at(D, ROW_STREAMS, e);
+  uint8_t* out = A.slots + S.slot_end;
+  const uint32_t* row = A.sym + (D.px_base + (int64_t)(S.ly * D.ph + S.r) * D.W + (int64_t)S.lx * D.pw) * 3;
+  uint32_t x = RANS_X0;
+  constexpr int B = 16;
+  uint32_t v[B];
+  for (int k = 3 * S.Wl - 1; k >= 0; k -= B) {
+    const int nb = min(B, k + 1);
+#pragma unroll
+    for (int m = 0; m < B; ++m) v[m] = m < nb ? row[k - m] : 0u;
+    rans_put(x, out, v, nb);
+  }
+  // the final state's significant bytes (x >= 1), most significant first
+  do {
+    *--out = (uint8_t)x;
+    x >>= 8;
+  } while (x != 0u);
+  A.lane_len[SL] = (uint32_t)((A.slots + S.slot_end) - out);
+}
+
 // ------------------------------------------------------------------ container assembly
 // per image: lane_end (inclusive prefix of lane lengths), container bytes
 __global__ void __launch_bounds__(256) k_lane_scan(PackArgs A) {
@@ -389,8 +469,8 @@ __global__ void __launch_bounds__(256) k_lane_scan(PackArgs A) {
   __shared__ uint32_t carry;
   const int n = blockIdx.x;
   const ImgDesc D = A.desc[n];
-  const int nl = D.nlx * D.nly * A.K;  // streams of this image
-  const int64_t sbase = D.lane_base * A.K;
+  const int nl = (int)image_streams(A.K, D.H, D.nlx, D.nly);  // streams of this image
+  const int64_t sbase = D.stream_base;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int b0 = 0; b0 < nl; b0 += 256) {
@@ -427,23 +507,17 @@ __global__ void k_img_scan(PackArgs A) {
 __global__ void __launch_bounds__(64) k_pack(PackArgs A) {
   if (*A.overflow) return;
   const int64_t SL = blockIdx.x;
-  const int64_t L = SL / A.K;
-  const int kk = (int)(SL - L * A.K);
-  const int n = find_img(A.desc, A.n_img, L, true);
+  const int n = find_img_stream(A.desc, A.n_img, SL);
   const ImgDesc D = A.desc[n];
-  const int q = (int)(L - D.lane_base);
+  const int64_t entry = SL - D.stream_base;
+  const int64_t ns = image_streams(A.K, D.H, D.nlx, D.nly);
   const int nl = D.nlx * D.nly;
-  const int ly = q / D.nlx, lx = q - ly * D.nlx;
-  const int y0 = ly * D.ph;
-  const int Hl = min(D.ph, D.H - y0), Wl = min(D.pw, D.W - lx * D.pw);
-  const int64_t lane_px_off = (int64_t)ly * D.ph * D.W + (int64_t)lx * D.pw * Hl;
-  const int64_t slot_end = D.slot_base + A.K * (6 * lane_px_off + 8 * (int64_t)q) +
-                           (kk + 1) * lane_slot_bytes((int64_t)Hl * Wl);
+  const StreamAt S = stream_at(D, A.K, entry);
+  const int64_t slot_end = S.slot_end;
   const uint32_t len = A.lane_len[SL];
   const uint32_t end = A.lane_end[SL];
-  const int64_t entry = (int64_t)q * A.K + kk;
   uint8_t* C = A.out + A.out_offsets[n];
-  uint8_t* dst = C + HDR_BYTES + 4 * (int64_t)nl * A.K + (end - len);
+  uint8_t* dst = C + HDR_BYTES + 4 * ns + (end - len);
   const uint8_t* src = A.slots + slot_end - len;
   for (uint32_t k = threadIdx.x; k < len; k += 64) dst[k] = src[k];
   if (threadIdx.x < 4) C[HDR_BYTES + 4 * entry + threadIdx.x] = (uint8_t)(end >> (8 * threadIdx.x));
@@ -613,6 +687,66 @@ struct PixStream {
   uint32_t len, pos, x;
 };
 
+// One symbol of every pixel of a 16-row group, each from the pixel's own
+// stream, all pixels at once: eight halvings of [0, 256], each the encoder's
+// evaluation of the quantised CDF (cdf_eval, all lanes of a pixel in step),
+// keeping the bracket's CDF values, so (start, freq) are bitwise the
+// encoder's. Pixels with act pop (state and position updated); the stream's
+// next two bytes are loaded before the search (clamped into the stream,
+// used only while bytes remain). Every lane must call it (lane-group sums).
+NXD int pop_own(const Chan& Q, PixStream& P, bool act, uint32_t& start, uint32_t& freq) {
+  const uint32_t lm = P.len - 1u;
+  const uint32_t nb0 = P.S[min(P.pos, lm)];
+  const uint32_t nb1 = P.S[min(P.pos + 1u, lm)];
+  // a state below 2^16 (the end of the stream) holds a spread slot
+  const bool small = P.x < CDF_TOTAL;
+  const uint32_t slot = small ? rev16(P.x) : (P.x & 0xffffu);
+  int lo = 0, hi = 256;
+  uint32_t clo = 0u, chi = CDF_TOTAL;
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int mid = (lo + hi) >> 1;
+    const uint32_t v = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b));
+    const bool le = v <= slot;
+    lo = le ? mid : lo;
+    clo = le ? v : clo;
+    hi = le ? hi : mid;
+    chi = le ? chi : v;
+  }
+  freq = chi - clo;
+  start = clo;
+  uint32_t xn = freq * (P.x >> 16) + slot - clo;
+  if (__ballot(small && act) != 0ull) {  // rare: a stream's last few pops
+    const uint32_t xr = spread_rank(P.x, clo, freq);
+    xn = small ? xr : xn;
+  }
+  uint32_t pn = P.pos;
+  const bool r0 = xn < RANS_L && pn < P.len;
+  xn = r0 ? ((xn << 8) | nb0) : xn;
+  pn += r0 ? 1u : 0u;
+  const bool r1 = xn < RANS_L && pn < P.len;
+  xn = r1 ? ((xn << 8) | nb1) : xn;
+  pn += r1 ? 1u : 0u;
+  P.x = act ? xn : P.x;
+  P.pos = act ? pn : P.pos;
+  return lo;
+}
+
+// a stream's initial state: its first bytes, most significant first, read
+// while x < L (at most four; loads clamped into the stream, len >= 1)
+NXD void stream_begin(PixStream& P) {
+  uint32_t xs = 0u, ps = 0u;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t byte = P.S[min((uint32_t)b, P.len - 1u)];
+    const bool rd = xs < RANS_L && ps < P.len;
+    xs = rd ? ((xs << 8) | byte) : xs;
+    ps += rd ? 1u : 0u;
+  }
+  P.x = xs;
+  P.pos = ps;
+}
+
 // K: rANS streams of the lane; the chain pops K symbols (rows ts + q0 + k,
 // streams k) per iteration, their searches independent of each other;
 // K >= 8: every row of a group pops from its own stream at once, found by a
@@ -717,18 +851,7 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
   }
   if constexpr (SAMPLE) {
   } else if constexpr (K >= 8) {
-    // the initial state: the stream's first bytes, most significant first,
-    // read while x < L (at most four; loads clamped into the stream)
-    uint32_t xs = 0u, ps = 0u;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const uint32_t byte = PS.S[min((uint32_t)b, PS.len - 1u)];
-      const bool rd = xs < RANS_L && ps < PS.len;
-      xs = rd ? ((xs << 8) | byte) : xs;
-      ps += rd ? 1u : 0u;
-    }
-    PS.x = xs;
-    PS.pos = ps;
+    stream_begin(PS);
   } else if constexpr (K == 4) {
     // the initial state: the stream's first bytes, most significant first,
     // read while x < L (at most four)
@@ -852,58 +975,22 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           else if (c == 1) xv[1] = lo;
           else xv[2] = lo;
         } else if constexpr (K >= 8) {
-          // every pixel's symbol from its own stream: eight halvings of [0,
-          // 256] over the group at once, each the encoder's evaluation of the
-          // quantised CDF (cdf_eval), keeping the bracket's CDF values, so
-          // (start, freq) are bitwise the encoder's; K = 8 pops rows 0..7,
-          // then rows 8..15
+          // every pixel's symbol from its own stream (pop_own); K = 8 pops
+          // rows 0..7, then rows 8..15
 #pragma unroll
           for (int half = 0; half < 16 / K; ++half) {
             const int q0 = half * K;
             if (q0 >= na) break;
             const bool act = p >= q0 && p < q0 + K && p < na;
-            // the two bytes a renormalisation may read, fetched ahead of the
-            // search (clamped into the stream, used only while bytes remain)
-            const uint32_t lm = PS.len - 1u;
-            const uint32_t nb0 = PS.S[min(PS.pos, lm)];
-            const uint32_t nb1 = PS.S[min(PS.pos + 1u, lm)];
-            // a state below 2^16 (the end of the stream) holds a spread slot
-            const bool small = PS.x < CDF_TOTAL;
-            const uint32_t slot = small ? rev16(PS.x) : (PS.x & 0xffffu);
-            int lo = 0, hi = 256;
-            uint32_t clo = 0u, chi = CDF_TOTAL;
-#pragma unroll
-            for (int it = 0; it < 8; ++it) {
-              const int mid = (lo + hi) >> 1;
-              const uint32_t v = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b));
-              const bool le = v <= slot;
-              lo = le ? mid : lo;
-              clo = le ? v : clo;
-              hi = le ? hi : mid;
-              chi = le ? chi : v;
-            }
-            const uint32_t freq = chi - clo;
-            uint32_t xn = freq * (PS.x >> 16) + slot - clo;
-            if (__ballot(small && act) != 0ull) {  // rare: a stream's last few pops
-              const uint32_t xr = spread_rank(PS.x, clo, freq);
-              xn = small ? xr : xn;
-            }
-            uint32_t pn = PS.pos;
-            const bool r0 = xn < RANS_L && pn < PS.len;
-            xn = r0 ? ((xn << 8) | nb0) : xn;
-            pn += r0 ? 1u : 0u;
-            const bool r1 = xn < RANS_L && pn < PS.len;
-            xn = r1 ? ((xn << 8) | nb1) : xn;
-            pn += r1 ? 1u : 0u;
-            PS.x = act ? xn : PS.x;
-            PS.pos = act ? pn : PS.pos;
+            uint32_t start, freq;
+            const int sy = pop_own(Q, PS, act, start, freq);
             if (act) {
-              if (c == 0) xv[0] = lo;
-              else if (c == 1) xv[1] = lo;
-              else xv[2] = lo;
+              if (c == 0) xv[0] = sy;
+              else if (c == 1) xv[1] = sy;
+              else xv[2] = sy;
             }
             if (TRACE && act && g == 0)
-              dump[((int64_t)(y0 + i) * D.W + (x0 + j)) * 3 + c] = clo | (freq << 16);
+              dump[((int64_t)(y0 + i) * D.W + (x0 + j)) * 3 + c] = start | (freq << 16);
             if constexpr (K == 8) {
               // rows p and p + 8 share a stream: the other half takes the new state
               const uint32_t ox = (uint32_t)__shfl_xor((int)PS.x, 8);
@@ -1128,9 +1215,224 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
   }
 }
 
-__global__ void k_decode_prep(int32_t* status, int n_img, int32_t* counter) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// ------------------------------------------------------------------ row streams
+// Row streams (one rANS stream per lane row): a lane is decoded in bands of
+// ROW_BAND rows, one workgroup of ROW_WAVES waves per band. At wavefront step
+// t the band's rows of the step are cut into groups of 16, one per wave; each
+// row pops its own stream, so every row of a step decodes at once (the whole
+// step of Algorithm 1 in parallel). A row's coder state lives in LDS between
+// steps (rows move from wave to wave as the step's first row advances).
+// A band's top rows read the h rows above, decoded by the band above it,
+// possibly on another CU: each band publishes how many steps it has finished
+// (release), and waits before step t until the band above has finished step
+// t - 1 (acquire). Bands are taken from the queue in order, so the band above
+// is always held by a running workgroup; its skew of (h + 1) ROW_BAND steps
+// makes waits rare once a band has started. A wait also ends, with the image
+// marked corrupt, if it exceeds BAND_WAIT_TICKS of the 100 MHz clock, so
+// every workgroup reaches the end of the kernel whatever happens.
+constexpr int32_t BAND_DONE = 0x7fffffff;
+constexpr uint64_t BAND_WAIT_TICKS = 2000000000ull;  // 20 s
+
+struct RowState {
+  uint32_t x, pos, start, len;  // coder state, position, and the row stream's bytes in the payload
+};
+
+NXD int find_img_band(const ImgDesc* __restrict__ d, int n, int64_t key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = uniform64(d[mid].band_base);
+    if (b <= key) lo = mid; else hi = mid - 1;
+  }
+  return uniform(lo);
+}
+
+NXD void band_publish(int32_t* slot, int32_t v) {
+  __hip_atomic_store(slot, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int H_, int C_, bool TRACE>
+__device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int32_t* sh, int64_t B) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, g = lane >> 4;
+  const bool has2 = g < 2;
+  const int n = find_img_band(A.desc, A.n_img, B);
+  const ImgDesc D = uniform_desc(A.desc + n);
+  // which lane of the image and which band of it: lanes in order, full patch
+  // rows first, each lane cut into bands_of(Hl) bands
+  const int64_t bi = B - D.band_base;
+  const int64_t per_prow = (int64_t)D.nlx * bands_of(D.ph);
+  const int ly = (int)(bi / per_prow);
+  const int y0 = ly * D.ph, Hl = min(D.ph, D.H - y0);
+  const int64_t rem = bi - (int64_t)ly * per_prow;
+  const int lx = (int)(rem / bands_of(Hl)), bb = (int)(rem - (int64_t)lx * bands_of(Hl));
+  const int x0 = lx * D.pw, Wl = min(D.pw, D.W - x0);
+  const int q = ly * D.nlx + lx, nl = D.nlx * D.nly;
+  const int r0 = bb * ROW_BAND, r1 = min(Hl, r0 + ROW_BAND) - 1, nrows = r1 - r0 + 1;
+  int32_t* mine = A.progress + B;
+  // header and stream table (every lane reads the same bytes)
+  const uint8_t* C = A.in + uniform64((int64_t)A.in_off[n]);
+  const int64_t clen = uniform64((int64_t)(A.in_off[n + 1] - A.in_off[n]));
+  const int64_t ns = image_streams(ROW_STREAMS, D.H, D.nlx, D.nly);
+  const int64_t pay = HDR_BYTES + 4 * ns;
+  bool ok = clen >= pay;
+  bool mismatch = false;
+  if (ok) {
+    const uint32_t ph = D.ph == D.H ? 0u : (uint32_t)D.ph, pw = D.pw == D.W ? 0u : (uint32_t)D.pw;
+    ok = C[0] == 'N' && C[1] == 'L' && C[2] == 'X' && C[3] == 'C' && C[4] == CONTAINER_VERSION && C[5] == 1 &&
+         C[6] == (uint8_t)H_ && C[7] == (uint8_t)ROW_STREAMS && rd_u32(C + 8) == (uint32_t)D.H &&
+         rd_u32(C + 12) == (uint32_t)D.W && (uint32_t)(C[16] | (C[17] << 8)) == ph &&
+         (uint32_t)(C[18] | (C[19] << 8)) == pw && rd_u32(C + 28) == (uint32_t)nl;
+    ok = ok && pay + (int64_t)rd_u32(C + HDR_BYTES + 4 * (ns - 1)) == clen;
+    ok = uniform(ok ? 1 : 0) != 0;
+    if (ok) {
+      const uint64_t hsh = (uint64_t)rd_u32(C + 20) | ((uint64_t)rd_u32(C + 24) << 32);
+      mismatch = uniform(hsh != A.model_hash ? 1 : 0) != 0;
+    }
+  }
+  // the band's rows: stream table entries, initial states
+  const int64_t ebase = row_entry_base(ly, lx, D.nlx, D.ph, Hl) + r0;
+  if (threadIdx.x == 0) sh[0] = 1;
+  __syncthreads();
+  if (ok && !mismatch) {
+    for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
+      const int64_t e = ebase + k;
+      const uint32_t lend = rd_u32(C + HDR_BYTES + 4 * e);
+      const uint32_t lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
+      const bool okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
+      PixStream P;
+      P.S = as_global(C + pay + (okr ? lstart : 0u));
+      P.len = okr ? lend - lstart : 1u;
+      stream_begin(P);
+      rs[k] = RowState{P.x, P.pos, okr ? lstart : 0u, P.len};
+      if (!okr) sh[0] = 0;
+    }
+  }
+  __syncthreads();
+  ok = ok && sh[0] != 0;
+  if (mismatch || !ok) {
+    if (threadIdx.x == 0) {
+      A.status[n] = mismatch ? ST_MISMATCH : ST_CORRUPT;
+      band_publish(mine, BAND_DONE);  // the band below must not wait for this one
+    }
+    __syncthreads();
+    return;
+  }
+  uint8_t* img = D.px;
+  const int o = H_ + 1;
+  const int t_lo = o * r0, t_hi = (Wl - 1) + o * r1;
+  uint32_t* dump = TRACE ? A.sym_dump + D.px_base * 3 : nullptr;
+  TapCodes<H_> tc;
+  tc.init(g);
+  int32_t seen = bb == 0 ? BAND_DONE : 0;  // steps of the band above known to be finished
+  for (int t = t_lo; t <= t_hi; ++t) {
+    if (seen < t) {
+      // wait until the band above has finished step t - 1
+      if (threadIdx.x == 0) {
+        const int32_t* above = A.progress + (B - 1);
+        int32_t v = __hip_atomic_load(above, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v < t) {
+          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+          while (v < t) {
+            __builtin_amdgcn_s_sleep(4);
+            v = __hip_atomic_load(above, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (v < t && __builtin_amdgcn_s_memrealtime() - t0 > BAND_WAIT_TICKS) {
+              A.status[n] = ST_CORRUPT;  // never expected: the image cannot be trusted
+              v = BAND_DONE;
+            }
+          }
+        }
+        sh[1] = v;
+      }
+      __syncthreads();
+      seen = sh[1];
+    }
+    // this band's step t - 1 is finished in every wave (pixels, row states)
+    __syncthreads();
+    if (threadIdx.x == 0) band_publish(mine, t);
+    int ilo, ihi;
+    step_rows(t, Hl, Wl, o, ilo, ihi);
+    const int a = max(ilo, r0), bmax = min(ihi, r1);
+    const int ts = a + 16 * wave;
+    if (ts > bmax) continue;
+    const int na = min(16, bmax - ts + 1);
+    const int i = ts + p;
+    const bool active = p < na;
+    const int j = t - o * i;
+    float ctx[conv_chunks(H_)];
+    tc.refresh();
+    gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
+    f4 head[HEAD_TILES];
+    net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
+    Mix M;
+    mix_prep(head, M, has2);
+    // the row's stream
+    const int k = min(i, bmax) - r0;
+    const RowState R = rs[k];
+    PixStream P;
+    P.S = as_global(C + pay + R.start);
+    P.len = R.len;
+    P.x = R.x;
+    P.pos = R.pos;
+    int xv[3] = {0, 0, 0};
+    float xr = 0.0f, xg = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Chan Q;
+      chan_params(M, c, xr, xg, Q);
+      uint32_t start, freq;
+      const int sy = pop_own(Q, P, active, start, freq);
+      if (c == 0) xv[0] = sy;
+      else if (c == 1) xv[1] = sy;
+      else xv[2] = sy;
+      if (TRACE && active && g == 0)
+        dump[((int64_t)(y0 + i) * D.W + (x0 + j)) * 3 + c] = start | (freq << 16);
+      if (c == 0) {
+        posterior(M, xv[0], Q.mu, Q.is, has2);
+        xr = normalise(xv[0]);
+      } else if (c == 1) {
+        posterior(M, xv[1], Q.mu, Q.is, has2);
+        xg = normalise(xv[1]);
+      }
+    }
+    if (active && g == 0) {
+      uint8_t* dst = img + ((int64_t)(y0 + i) * D.W + (x0 + j)) * 3;
+      dst[0] = (uint8_t)xv[0];
+      dst[1] = (uint8_t)xv[1];
+      dst[2] = (uint8_t)xv[2];
+      rs[k] = RowState{P.x, P.pos, R.start, R.len};
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) band_publish(mine, BAND_DONE);
+  // every row's stream must end in the start state with every byte read
+  bool clean = true;
+  for (int k = threadIdx.x; k < nrows; k += blockDim.x) clean = clean && rs[k].x == RANS_X0 && rs[k].pos == rs[k].len;
+  if (!clean) A.status[n] = ST_CORRUPT;
+  __syncthreads();
+}
+
+template <int H_, int C_, bool TRACE>
+__global__ void __launch_bounds__(ROW_WAVES * 64) k_decode_rows(DecArgs A) {
+  extern __shared__ float4 smem_f4[];
+  float* w = (float*)smem_f4;
+  load_weights(w, A.w, A.wfloats);
+  RowState* rs = (RowState*)(w + A.wfloats);
+  int32_t* sh = (int32_t*)(rs + ROW_BAND);  // band, wait and flag words shared by the workgroup
+  for (;;) {
+    if (threadIdx.x == 0) sh[2] = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int64_t B = sh[2];
+    __syncthreads();
+    if (B >= A.n_bands) break;
+    decode_band<H_, C_, TRACE>(A, w, rs, sh, B);
+  }
+}
+
+__global__ void k_decode_prep(int32_t* status, int n_img, int32_t* counter, int32_t* progress, int64_t n_bands) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (status && i < n_img) status[i] = ST_OK;
+  if (progress && i < n_bands) progress[i] = 0;
   if (i == 0) *counter = 0;
 }
 
@@ -1224,7 +1526,9 @@ bool supported(int h, int C) {
 // kernels keep the whole weight image in LDS: allow up to the device limit
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t lds) {
-  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) (void)hipGetLastError();  // reported here, not by the next launch's check
+  return e;
 }
 
 template <int H_, int C_>
@@ -1265,6 +1569,14 @@ static hipError_t decode_setup_k() {
 
 template <int H_, int C_>
 static hipError_t decode_setup(int K) {
+  if (K == ROW_STREAMS) {
+    int dev = 0, lim = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess) e = allow_lds(k_decode_rows<H_, C_, false>, (size_t)lim);
+    if (e == hipSuccess) e = allow_lds(k_decode_rows<H_, C_, true>, (size_t)lim);
+    return e;
+  }
   if (K == 2) return decode_setup_k<H_, C_, 2>();
   if (K == 4) return decode_setup_k<H_, C_, 4>();
   if (K == 8) return decode_setup_k<H_, C_, 8>();
@@ -1332,6 +1644,10 @@ static void launch_layout(const RansEncArgs& a, hipStream_t s) {
 
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   if (a.n_lanes == 0) return hipSuccess;
+  if (a.K == ROW_STREAMS) {
+    hipLaunchKernelGGL(k_rans_enc_rows, dim3((unsigned)((a.n_streams + 63) / 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
   if (a.h < 1 || a.h > 3 || !valid_interleave(a.K)) return hipErrorInvalidValue;
   const int kx = a.K == 1 ? 0 : a.K == 2 ? 1 : a.K == 4 ? 2 : a.K == 8 ? 3 : 4;
   switch (5 * (a.h - 1) + kx) {
@@ -1353,7 +1669,7 @@ hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int grid = (int)((a.n_lanes * a.K + 63) / 64);
+  const int grid = (int)((a.n_streams + 63) / 64);
   hipLaunchKernelGGL(k_rans_enc, dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
@@ -1361,14 +1677,31 @@ hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s) {
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_lane_scan, dim3(a.n_img), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_img_scan, dim3(1), dim3(64), 0, s, a);
-  if (a.n_lanes > 0) hipLaunchKernelGGL(k_pack, dim3((unsigned)(a.n_lanes * a.K)), dim3(64), 0, s, a);
+  if (a.n_streams > 0) hipLaunchKernelGGL(k_pack, dim3((unsigned)a.n_streams), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s) {
-  const int grid = (n_img + 255) / 256 > 0 ? (n_img + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_decode_prep, dim3(grid), dim3(256), 0, s, status, n_img, counter);
+hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s, int32_t* progress,
+                              int64_t n_bands) {
+  const int64_t items = std::max<int64_t>(std::max<int64_t>(n_img, n_bands), 1);
+  hipLaunchKernelGGL(k_decode_prep, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, status, n_img, counter,
+                     progress, n_bands);
   return hipGetLastError();
+}
+
+template <int H_, int C_>
+static hipError_t rows_t(const DecArgs& a, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.wfloats * 4 + ROW_BAND * sizeof(RowState) + 4 * sizeof(int32_t);
+  if (a.sym_dump)
+    hipLaunchKernelGGL((k_decode_rows<H_, C_, true>), dim3(grid), dim3(ROW_WAVES * 64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_decode_rows<H_, C_, false>), dim3(grid), dim3(ROW_WAVES * 64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_rows(int h, int C, const DecArgs& a, int grid, hipStream_t s) {
+  if (a.n_bands == 0) return hipSuccess;
+  NX_DISPATCH(rows_t, h, C, a, grid, s);
 }
 
 hipError_t launch_reduce_bits(const ImgDesc* desc, int n_img, const float* bits, double* partials, double* out,

@@ -31,9 +31,10 @@ struct RansEncArgs {
   const ImgDesc* desc;
   int n_img;
   int64_t n_lanes;
+  int64_t n_streams;       // rANS streams of the batch (n_lanes K, or the lane rows)
   int order;               // 0 raster, 1 wavefront
   int h;
-  int K;                   // rANS streams per lane
+  int K;                   // rANS streams per lane (ROW_STREAMS: one per lane row)
   const uint32_t* sym;
   uint8_t* slots;
   uint32_t* lane_len;      // symbols per stream (gather), then bytes per stream (encoder)
@@ -48,11 +49,12 @@ struct PackArgs {
   const ImgDesc* desc;
   int n_img;
   int64_t n_lanes;
+  int64_t n_streams;       // rANS streams of the batch
   int order, h;
-  int K;                   // rANS streams per lane (entries of the stream table per lane)
+  int K;                   // rANS streams per lane (ROW_STREAMS: one per lane row)
   uint64_t model_hash;
   const uint8_t* slots;
-  const uint32_t* lane_len;  // per stream (lane q K + k)
+  const uint32_t* lane_len;  // per stream (global stream index, image n's from desc[n].stream_base)
   uint32_t* lane_end;      // scratch: cumulative payload bytes per stream
   uint64_t* img_bytes;     // scratch: container bytes per image
   uint8_t* out;
@@ -78,6 +80,8 @@ struct DecArgs {
   uint32_t* sym_dump;      // nullable: (start | freq << 16) used per pixel/channel
   uint8_t* ring;           // order 2: grid x waves context rings of ring_wave_bytes(ring_rows)
   int ring_rows;
+  int32_t* progress;       // row streams: per band, the steps it has finished (zeroed by the prep)
+  int64_t n_bands;         // row streams: bands of the batch (the queue's work items)
 };
 
 // Training objective and gradient (nx_train.hip). n images of H x W, all
@@ -130,7 +134,11 @@ bool supported(int h, int C);
 hipError_t launch_pass(int h, int C, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
-hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s);
+hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s,
+                              int32_t* progress = nullptr, int64_t n_bands = 0);
+// row streams: the band decoder (ROW_BAND / 16 waves per workgroup, one band at a time)
+constexpr int ROW_WAVES = ROW_BAND / 16;
+hipError_t launch_decode_rows(int h, int C, const DecArgs& a, int grid, hipStream_t s);
 // raise the decoder kernels' LDS limit (once, outside any stream capture)
 hipError_t prepare_decode(int h, int C, int K);
 // waves per workgroup in 1..DECODE_WAVES (the LDS takes one pivot table per wave);

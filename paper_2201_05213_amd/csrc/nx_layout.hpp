@@ -63,8 +63,32 @@ struct ImgDesc {
   uint64_t seed;       // sampling: key word 0 of the image's Philox stream
   int64_t rev_base;    // encoder: first word of this image's streams in the coding-order symbol buffer
   int64_t after_base;  // encoder: first entry of this image's streams in the per-step offset table
+  int64_t stream_base; // first global rANS stream index of this image (lane_base K with K streams per lane)
+  int64_t band_base;   // row streams: first global band index of this image
 };
-static_assert(sizeof(ImgDesc) == 96, "descriptor layout");
+static_assert(sizeof(ImgDesc) == 112, "descriptor layout");
+
+// Row streams (opts.interleave = -1, K = 0 inside the library, 0 in the
+// container's stream byte): every row of every lane is its own rANS stream,
+// its symbols the row's pixels left to right, R, G, B. The stream table
+// holds a lane's rows in order, lanes in order: lane (ly, lx) of a patch grid
+// nlx wide with patch rows ph starts at entry ly nlx ph + lx Hl, Hl its rows.
+constexpr int ROW_STREAMS = 0;
+NXHD int64_t row_entry_base(int ly, int lx, int nlx, int ph, int Hl) {
+  return (int64_t)ly * nlx * ph + (int64_t)lx * Hl;
+}
+// a lane's rows are decoded in bands of ROW_BAND rows, one workgroup of
+// ROW_BAND / 16 waves each, a band waiting on the progress of the one above
+constexpr int ROW_BAND = 64;
+NXHD int bands_of(int Hl) { return (Hl + ROW_BAND - 1) / ROW_BAND; }
+// streams and bands of an image of H rows with a grid of nlx x nly patches of ph rows
+NXHD int64_t image_streams(int K, int H, int nlx, int nly) {
+  return K == ROW_STREAMS ? (int64_t)nlx * H : (int64_t)nlx * nly * K;
+}
+NXHD int64_t image_bands(int H, int ph, int nlx, int nly) {
+  const int last = H - (nly - 1) * ph;
+  return (int64_t)nlx * ((int64_t)(nly - 1) * bands_of(ph) + bands_of(last));
+}
 
 // Encoder scratch per rANS stream of a lane of at most ph x pw pixels (K
 // streams per lane): its symbols in coding order, 3 (ph pw / K + T) words
@@ -108,6 +132,8 @@ constexpr uint8_t CONTAINER_VERSION = 2;
 constexpr uint8_t CODER_RANS8 = 1;
 constexpr int MAX_INTERLEAVE = 16;
 NXHD bool valid_interleave(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16; }
+// the container's stream byte: K, or 0 for row streams
+NXHD bool valid_stream_code(int k) { return k == ROW_STREAMS || valid_interleave(k); }
 //  0 "NLXC" | 4 u8 version | 5 u8 order | 6 u8 h | 7 u8 K | 8 u32 H | 12 u32 W
 // 16 u16 patch_h (0 = whole) | 18 u16 patch_w (0 = whole) | 20 u64 model hash
 // 28 u32 n_lanes
