@@ -443,6 +443,61 @@ def main():
     log(f"[bench] raster: {rows}x1024 strip {strip_s:.3f}s -> {raster_pxs:.0f} px/s, "
         f"1024^2 extrapolated {raster_full_s:.1f}s")
 
+    # the paper's exact method: whole-image lanes (no patch borders), one rANS
+    # stream per image row, every row of a wavefront step at once, bands of 64
+    # rows pipelined across CUs; one 1024^2 image alone (latency, against the
+    # raster decode) and the whole batch (throughput, bits/dim against the
+    # oracle's whole-image ideal when tests/golden/patch_cost.json holds it)
+    whole_rec = {}
+    for wname, wm in (("B", m), ("B_trained", None)):
+        if wm is None:
+            tpath = os.path.join(ROOT, "tests", "golden", "model_b_trained.nlxw")
+            if not os.path.exists(tpath):
+                continue
+            with open(tpath, "rb") as f:
+                wm = nx.Model(f.read())
+        rd, ro = wm.encode(ts, order=nx.WAVEFRONT, interleave=nx.ROWS)
+        rplan, rws = wm.decode_prepare(outs, order=nx.WAVEFRONT, interleave=nx.ROWS)
+        wm.decode_run(rplan, rd, ro, status, rws)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(3):
+            wm.decode_run(rplan, rd, ro, status, rws)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts)) and int(status.abs().sum()) == 0
+        batch_ms = ev[0].elapsed_time(ev[1]) / 3
+        rbits = float(sum(nx.payload_bits(rd, ro)))
+        # one 1024^2 image alone
+        r1d, r1o = wm.encode([ts[0]], order=nx.WAVEFRONT, interleave=nx.ROWS)
+        p1, w1 = wm.decode_prepare([outs[0]], order=nx.WAVEFRONT, interleave=nx.ROWS)
+        st1 = status[:1]
+        wm.decode_run(p1, r1d, r1o, st1, w1)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(3):
+            wm.decode_run(p1, r1d, r1o, st1, w1)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], ts[0]) and int(st1.abs().sum()) == 0
+        one_ms = ev[0].elapsed_time(ev[1]) / 3
+        rec = {"one_1024_ms": one_ms, "speedup_vs_raster_1024": None, "batch_ms": batch_ms,
+               "batch_px_per_s": npx / batch_ms * 1e3, "bits_per_dim": rbits / (3 * npx),
+               "bands": int(rplan.n_bands)}
+        opath = os.path.join(ROOT, "tests", "golden", "patch_cost.json")
+        if os.path.exists(opath):
+            with open(opath) as f:
+                ores = json.load(f)["results"]
+            if wname in ores:
+                ideal = ores[wname]["large6"]["whole"]["qbits"]
+                rec["gap_vs_oracle_whole_image_ideal"] = (rbits - ideal) / ideal
+        whole_rec[wname] = rec
+        del rws, w1
+        log(f"[bench] whole-image lanes, row streams, model {wname}: one 1024^2 image {one_ms:.1f} ms; batch "
+            f"{batch_ms:.1f} ms ({npx / batch_ms / 1e3:.0f} Mpx/s, {rplan.n_bands} bands); "
+            f"{rbits / (3 * npx):.4f} bits/dim" + (f", gap {100 * rec['gap_vs_oracle_whole_image_ideal']:.4f}% vs "
+            f"the oracle's whole-image ideal" if "gap_vs_oracle_whole_image_ideal" in rec else ""))
+
     # bits/dim: coded lane payloads vs the oracle's quantised ideal on sampled lanes
     cont = data.cpu().numpy()
     offs_h = offs.cpu().numpy()
@@ -616,6 +671,8 @@ def main():
         with open(opath) as f:
             patch_cost["oracle"] = json.load(f)["results"]
 
+    for rec in whole_rec.values():
+        rec["speedup_vs_raster_1024"] = raster_full_s / (rec["one_1024_ms"] / 1e3)
     out = {
         "metric": "decoded pixels/sec on 1 GPU, wavefront+patch vs raster; bits/dim gap vs FP64 oracle",
         "value": value,
@@ -643,6 +700,7 @@ def main():
         "raster_1024_s_extrapolated": raster_full_s,
         "raster_sample": f"{rows}x1024 strip, raster order, one lane, scaled by 1024/{rows}",
         "one_1024_wavefront_patch_s": one_s,
+        "whole_image_row_streams": whole_rec,
         "speedup_vs_raster_1024": raster_full_s / one_s,
         "batch_px_per_s_vs_raster": value / raster_pxs,
         "encode_s_untimed": enc_s,
