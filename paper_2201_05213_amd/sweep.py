@@ -2,8 +2,11 @@
 raster decoder against the wavefront decoder (Sec. 3, Algorithm 1), whole
 image and with patches, in the manner of the paper's Table 2 (decode time
 per image for 0/1/3 residual blocks at 32x32, and for image sides 32 to
-1024 with no block). Inputs are seeded smooth synthetic images; models are
-random-init local models with h = 3.
+1024 with no block). Inputs are the seeded smooth synthetic images of the
+shared input recipe; models are its random-init local models with h = 3.
+Whole images decode with one stream per lane (one wave per image) and with
+one stream per image row (the rows of a wavefront step decoded together, in
+pipelined bands of rows).
 
     python -m paper_2201_05213_amd.sweep > table.md
     python -m paper_2201_05213_amd.sweep --patches   # large batch: patch shape x streams
@@ -18,22 +21,17 @@ import numpy as np
 import torch
 
 import paper_2201_05213_amd as nx
+import synth
 
 __all__ = ["time_decode", "run"]
 
 
 def _images(n, H, W, seed):
-    """Seeded smooth fields (separable box-blurred noise, rescaled)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    out = []
-    for _ in range(n):
-        z = rng.standard_normal((H + 8, W + 8, 3))
-        k = np.ones(5) / 5.0
-        z = np.apply_along_axis(lambda v: np.convolve(v, k, mode="same"), 0, z)
-        z = np.apply_along_axis(lambda v: np.convolve(v, k, mode="same"), 1, z)[4:4 + H, 4:4 + W]
-        z = (z - z.min()) / max(z.max() - z.min(), 1e-9) * 255.0
-        out.append(np.ascontiguousarray(np.clip(np.rint(z), 0, 255).astype(np.uint8)))
-    return out
+    """Seeded smooth fields from the shared input recipe: up to 256 pixels a
+    side the small-image generator (Gaussian blur sigma 2, 3 step edges), above
+    it the large-image one (sigma 4, 20 edges, +-3 uniform noise)."""
+    sigma, edges, noise = (2.0, 3, 0) if max(H, W) <= 256 else (4.0, 20, 3)
+    return [synth.smooth_field_image(sigma, edges, noise, H, W, seed + k) for k in range(n)]
 
 
 def time_decode(m, imgs, order, patch=None, interleave=1, reps=3):
@@ -59,14 +57,9 @@ def time_decode(m, imgs, order, patch=None, interleave=1, reps=3):
 
 
 def _model(h, C, nb, seed):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    K = 2 * h + 1
-    shapes = [C * 3 * K * K, C] + [C * C, C, C * C, C] * nb + [100 * C, 100]
-    fans = [3 * K * K, 3 * K * K] + [C] * (4 * nb) + [C, C]
-    parts = [rng.uniform(-1 / np.sqrt(f), 1 / np.sqrt(f), size=n) for n, f in zip(shapes, fans)]
-    from .blob import blob_from_params
-
-    return nx.Model(blob_from_params((h, C, nb, 10), np.concatenate(parts).astype(np.float32)))
+    """Random-init local model from the shared weight recipe
+    (U(+-1/sqrt(fan_in)) for every weight and bias)."""
+    return nx.Model(synth.write_blob(h, C, nb, synth.init_params(h, C, nb, seed)))
 
 
 def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
@@ -86,8 +79,9 @@ def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
     pr("")
     pr(f"### Image size (h = 3, C = {C}, no block), decode time per image")
     pr("")
-    pr("| side | raster | wavefront, whole image | speedup | wavefront + 64x64 patches, 4 streams | speedup |")
-    pr("|---|---|---|---|---|---|")
+    pr("| side | raster | wavefront, whole image | speedup | whole image, row streams | speedup "
+       "| wavefront + 64x64 patches, 4 streams | speedup |")
+    pr("|---|---|---|---|---|---|---|---|")
     m = _model(3, C, 0, 100)
     for side in (32, 64, 128, 1024):
         img = [torch.from_numpy(i).to(dev) for i in _images(1, side, side, 11 + side)]
@@ -100,18 +94,18 @@ def run(C: int = 32, raster_rows: int = 8, out=sys.stdout):
             tr = time_decode(m, strip, nx.RASTER, reps=1) * side / raster_rows
             rnote = f" ({raster_rows}-row strip, scaled)"
         tw = time_decode(m, img, nx.WAVEFRONT, reps=2 if side > 128 else 3)
+        trw = time_decode(m, img, nx.WAVEFRONT, interleave=nx.ROWS)
         tp = time_decode(m, img, nx.WAVEFRONT, patch=(64, 64), interleave=4) if side >= 64 else float("nan")
         sp = f"{tp * 1e3:.2f} ms | {tr / tp:.0f}x" if side >= 64 else "n/a | n/a"
-        pr(f"| {side} | {tr * 1e3:.2f} ms{rnote} | {tw * 1e3:.2f} ms | {tr / tw:.1f}x | {sp} |")
+        pr(f"| {side} | {tr * 1e3:.2f} ms{rnote} | {tw * 1e3:.2f} ms | {tr / tw:.1f}x | {trw * 1e3:.2f} ms | "
+           f"{tr / trw:.0f}x | {sp} |")
 
 
 def run_patches(out=sys.stdout, shapes=((32, 64), (64, 64), (80, 64), (96, 64), (112, 64), (128, 64), (64, 96),
                                        (64, 128), (96, 96), (128, 128)),
-                streams=(4, 2, 1), reps=3):
+                streams=(16, 8, 4), reps=3):
     """Decode time of the large batch (4 x 1024^2 + 2 x 2048x1536, model B,
     wavefront order) by patch shape and rANS streams per lane."""
-    import synth
-
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pr = lambda s: print(s, file=out, flush=True)  # noqa: E731
@@ -139,7 +133,7 @@ if __name__ == "__main__":
                     help="instead: decode time of the large batch by patch shape and streams per lane")
     ap.add_argument("--shapes", default=None,
                     help="with --patches: comma-separated ROWSxCOLS patch shapes (default: a fixed set)")
-    ap.add_argument("--streams", default="4,2,1", help="with --patches: comma-separated streams per lane")
+    ap.add_argument("--streams", default="16,8,4", help="with --patches: comma-separated streams per lane")
     a = ap.parse_args()
     if a.patches:
         kw = {"streams": tuple(int(k) for k in a.streams.split(","))}

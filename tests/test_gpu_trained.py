@@ -123,3 +123,28 @@ def test_trained_gap(trained, case):
         small = imgs[0].shape[0] * imgs[0].shape[1] <= 32 * 32 or patch == (32, 32)
         if not (small and K == 4):
             assert gap <= 1e-3, (K, gap)
+
+
+def test_autotune_measures_bits_against_whole_image_coding(trained):
+    """With the trained model, patch borders cost bits (the oracle's figures
+    for the uneven batch: +5.4% at 86x64 patches, +6.5% at 64x64, +14.6% at
+    32x32, tests/golden/patch_cost.json), so the tuner, measuring bits
+    against whole-image coding, rejects every patched layout and picks a
+    whole-image one; the choice is within 0.1% of the fewest whole-image
+    bits and its streams cost under 0.1% of every image's bits."""
+    nx, m, _ = trained
+    from paper_2201_05213_amd import tune
+
+    ts = [torch.from_numpy(i).cuda() for i in synth.workload_images("uneven64", count=8)]
+    choice, table = tune.autotune(m, ts, interleaves=(1, 4, 16), reps=1)
+    for r in table:
+        say(f"[gpu] trained B autotune: patch {r['patch']} K={r['interleave']}: {r['decode_ms']:.2f} ms, "
+            f"{r['bits']} bits, streams {100 * r['stream_cost']:.4f}%, ok {r['ok']}")
+    assert len(table) == 3 * 3 + 1
+    ref = min(r["bits"] for r in table if r["patch"] is None)
+    for r in table:
+        if r["patch"] is not None:
+            assert r["bits"] > ref * 1.01 and not r["ok"], r
+    assert choice["ok"] and choice["patch"] is None
+    assert choice["bits"] <= ref * 1.001 and choice["stream_cost"] <= 1e-3
+    assert choice["decode_ms"] == min(r["decode_ms"] for r in table if r["ok"])

@@ -6,7 +6,7 @@ import math
 import pytest
 
 import synth
-from paper_2201_05213_amd import tune
+from paper_2201_05213_amd import ROWS, tune
 
 
 def test_lane_count_brute_force():
@@ -46,3 +46,37 @@ def test_balanced_patch_large_batch_on_256_cus():
     assert tune.lane_count(shapes, (84, 64)) == 2032
     # a batch far below the cap takes the floor
     assert tune.balanced_patch([(1024, 1024)], cus=256) == (64, 64)
+
+
+@pytest.mark.parametrize("K,bpd", [(16, 9.0), (16, 4.35), (8, 4.35), (4, 1.0)])
+def test_balanced_patch_stream_budget(K, bpd):
+    """With an expected bits/dim, a height is taken only if a full lane's K
+    streams cost at most 0.1% of its bits; every shorter height from 64 rows
+    breaks one of the rules."""
+    shapes = synth.workload_shapes("large6")
+    ph, pw = tune.balanced_patch(shapes, cus=256, interleave=K, bits_per_dim=bpd)
+    cap = 2 * 4 * 256
+
+    def fine(r):
+        tails = all(H <= r or H - (math.ceil(H / r) - 1) * r >= r / 2 for H, _ in shapes)
+        budget = K * tune.STREAM_BITS <= 1e-3 * 3 * r * 64 * bpd
+        return tune.lane_count(shapes, (r, 64)) <= cap and tails and budget
+
+    assert fine(ph)
+    assert not any(fine(r) for r in range(64, ph))
+    if (K, bpd) == (16, 9.0):
+        assert ph == 86  # the random-init model's ~9 bits/dim leaves the benchmark's patch
+    if (K, bpd) == (16, 4.35):
+        assert ph >= 96  # 80 bits per lane need at least 95.8 rows of 64 columns at 4.35 bits/dim
+
+
+def test_image_streams_count():
+    for (H, W), patch in itertools.product([(37, 29), (64, 64), (1, 200), (130, 7)],
+                                           [None, (1, 1), (16, 16), (64, 8)]):
+        lanes = tune.lane_count([(H, W)], (H, W) if patch is None else patch)
+        for K in (1, 2, 4, 8, 16):
+            assert tune.image_streams(H, W, patch, K) == lanes * K
+        # row streams: one per row of every lane
+        ph, pw = (H, W) if patch is None else patch
+        rows = sum(min(ph, H - y) for y in range(0, H, ph) for _ in range(0, W, pw))
+        assert tune.image_streams(H, W, patch, ROWS) == rows
