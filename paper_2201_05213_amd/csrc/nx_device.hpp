@@ -73,10 +73,12 @@ NXD float xtanh(float x) {
 
 // ELU with exp(x) - 1 from the hardware exp2 for x <= 0: the rounding of
 // x log2(e) costs a relative error of at most |x| 2^-24 ln2 in exp(x), i.e.
-// an absolute error below 3e-8 in the activation
+// an absolute error below 3e-8 in the activation. For x > 0 the exponent is
+// 0 and e = 0; for x <= 0, exp(x) - 1 >= x, so the larger of x and e is the
+// activation (x itself where rounding put e below it, |x| < 2^-23)
 NXD float xelu(float x) {
   const float e = __builtin_amdgcn_exp2f(fminf(x, 0.0f) * kLog2e) - 1.0f;
-  return x > 0.0f ? x : e;
+  return fmaxf(x, e);
 }
 
 // logistic sigmoid: monotone non-decreasing in z because the hardware exp2
@@ -100,36 +102,28 @@ NXD float bin_edge(int k) { return (float)(2 * k - 256) * (1.0f / 255.0f); }
 
 // ------------------------------------------------------------------ lane group reductions
 // A pixel's mixture is spread over its four lanes p + 16 g; these combine one
-// value per lane group with a fixed tree (v0 + v1) + (v2 + v3). IEEE addition
-// is commutative, so every lane of the pixel obtains the same bits. The
-// exchanges use the gfx950 row swaps (VALU, no LDS round trip):
-// permlane16_swap exchanges rows 0<->1 and 2<->3, permlane32_swap rows
-// 0,1 <-> 2,3.
-NXD float xor16(float v, int g) {
+// value per lane group with a fixed tree (v0 + v1) + (v2 + v3). The exchanges
+// use the gfx950 row swaps (VALU, no LDS round trip): permlane16_swap of a
+// value with itself leaves every lane holding its own value and that of its
+// partner row (0<->1, 2<->3), permlane32_swap that of its partner half (rows
+// 0,1 <-> 2,3); the pair is combined in either order, and IEEE addition and
+// max are commutative, so every lane of the pixel obtains the same bits.
+NXD float grp_sum(float v) {
   const uint32_t u = __float_as_uint(v);
   const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-  return __uint_as_float((g & 1) ? r[0] : r[1]);
-}
-NXD float xor32(float v, int g) {
-  const uint32_t u = __float_as_uint(v);
-  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-  return __uint_as_float((g & 2) ? r[0] : r[1]);
-}
-NXD int lane_group() { return (int)(__lane_id() >> 4); }
-
-NXD float grp_sum(float v) {
-  const int g = lane_group();
-  v = v + xor16(v, g);
-  v = v + xor32(v, g);
-  return v;
+  const float s = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  const uint32_t w = __float_as_uint(s);
+  const auto q = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 NXD float grp_max(float v) {
-  const int g = lane_group();
-  v = fmaxf(v, xor16(v, g));
-  v = fmaxf(v, xor32(v, g));
-  return v;
+  const uint32_t u = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  const float s = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+  const uint32_t w = __float_as_uint(s);
+  const auto q = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
 }
-
 // ------------------------------------------------------------------ gather
 // Causal context of pixel (i, j) of a lane (a rect of Hl x Wl pixels at (y0, x0)
 // of an image with row length W): input index k = 3 tap + ch over the taps in
@@ -417,7 +411,7 @@ NXD float cdf_eval(int k, const float (&w)[3], const float (&a)[3], const float 
 // Quantised CDF value: k + floor(clamp(F, 0, 1) * (2^16 - 256)). Monotone in
 // k whenever F is, with a step of at least 1 between consecutive symbols.
 NXD uint32_t cdf_quant(int k, float F) {
-  const float c = fminf(fmaxf(F, 0.0f), 1.0f);
+  const float c = __builtin_amdgcn_fmed3f(F, 0.0f, 1.0f);
   return (uint32_t)k + (uint32_t)(c * 65280.0f);
 }
 

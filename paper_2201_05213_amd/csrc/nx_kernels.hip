@@ -701,16 +701,17 @@ NXD int pop_own(const Chan& Q, PixStream& P, bool act, uint32_t& start, uint32_t
   // a state below 2^16 (the end of the stream) holds a spread slot
   const bool small = P.x < CDF_TOTAL;
   const uint32_t slot = small ? rev16(P.x) : (P.x & 0xffffu);
-  int lo = 0, hi = 256;
+  // the bracket [lo, lo + 2^(8 - it)) halves at every step: its midpoint is
+  // lo plus a constant, and only its CDF values need keeping
+  int lo = 0;
   uint32_t clo = 0u, chi = CDF_TOTAL;
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
-    const int mid = (lo + hi) >> 1;
+    const int mid = lo + (128 >> it);
     const uint32_t v = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b));
     const bool le = v <= slot;
     lo = le ? mid : lo;
     clo = le ? v : clo;
-    hi = le ? hi : mid;
     chi = le ? chi : v;
   }
   freq = chi - clo;
@@ -963,13 +964,12 @@ __device__ void decode_lane(const DecArgs& A, const float* w, uint32_t* piv, int
           // [0, 256] with cdf(0) = 0 <= slot < cdf(256) = 2^16 kept; the
           // evaluations are the encoder's (cdf_eval), so the draw is the
           // inverse of the coder's own row
-          int lo = 0, hi = 256;
+          int lo = 0;
 #pragma unroll
           for (int it = 0; it < 8; ++it) {
-            const int mid = (lo + hi) >> 1;
+            const int mid = lo + (128 >> it);
             const bool le = cdf_quant(mid, cdf_eval(mid, Q.w, Q.a, Q.b)) <= sl[c];
             lo = le ? mid : lo;
-            hi = le ? hi : mid;
           }
           if (c == 0) xv[0] = lo;
           else if (c == 1) xv[1] = lo;
