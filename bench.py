@@ -531,10 +531,10 @@ def main():
             pool.map(_oracle_job, [("stats", crops[0][:4, :4].copy())] * procs)  # workers up and loaded
             t0 = time.time()
             encs = pool.map(_oracle_job, [("enc", c) for c in crops], chunksize=1)
-            enc_s = time.time() - t0
+            cpu_enc_s = time.time() - t0
             t0 = time.time()
             pool.map(_oracle_job, [("dec", c, e) for c, e in zip(crops, encs)], chunksize=1)
-            dec_s = time.time() - t0
+            cpu_dec_s = time.time() - t0
             ideals = pool.map(_oracle_job, [("stats", c) for c in crops], chunksize=1)
         # the gap over every lane of image 0
         ideal, got = float(sum(ideals)), float(lane_bits.sum())
@@ -547,15 +547,15 @@ def main():
         for c, enc in zip(crops[:args.cpu_lanes], encs):
             dec = om.decode(enc, c.shape[0], c.shape[1], 1)
             assert np.array_equal(dec, c)
-        one_s = time.time() - c1
+        cpu1_s = time.time() - c1
         lpx = sum(c.shape[0] * c.shape[1] for c in crops)
         one_px = sum(c.shape[0] * c.shape[1] for c in crops[:args.cpu_lanes])
-        cpu = {"value": lpx / dec_s, "unit": "decoded px/s", "cores": procs, "kind": "oracle",
-               "encode_px_per_s": lpx / enc_s, "decode_px_per_s_1thread": one_px / one_s,
+        cpu = {"value": lpx / cpu_dec_s, "unit": "decoded px/s", "cores": procs, "kind": "oracle",
+               "encode_px_per_s": lpx / cpu_enc_s, "decode_px_per_s_1thread": one_px / cpu1_s,
                "nproc": os.cpu_count(), "usable_cpus": usable_cpus(), "cpu_model": cpu_model(),
                "sample": f"all {nl0} {pname} lanes of image 0 (1024x1024, {lpx} px), wavefront order, FP64 C "
-                         f"oracle, one lane per call in {procs} processes: encode {enc_s:.1f} s, decode "
-                         f"{dec_s:.1f} s; one thread: {args.cpu_lanes} lanes decoded in {one_s:.1f} s"}
+                         f"oracle, one lane per call in {procs} processes: encode {cpu_enc_s:.1f} s, decode "
+                         f"{cpu_dec_s:.1f} s; one thread: {args.cpu_lanes} lanes decoded in {cpu1_s:.1f} s"}
         log(f"[bench] oracle CPU ({procs} processes, {cpu['cpu_model']}): decode {cpu['value']:.0f} px/s, encode "
             f"{cpu['encode_px_per_s']:.0f} px/s; one thread decode {cpu['decode_px_per_s_1thread']:.0f} px/s")
 
