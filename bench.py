@@ -449,7 +449,7 @@ def main():
         f"1024^2 extrapolated {raster_full_s:.1f}s")
 
     # the paper's exact method: whole-image lanes (no patch borders), one rANS
-    # stream per image row, every row of a wavefront step at once, bands of 64
+    # stream per image row, every row of a wavefront step at once, bands of 16
     # rows pipelined across CUs; one 1024^2 image alone (latency, against the
     # raster decode) and the whole batch (throughput, bits/dim against the
     # oracle's whole-image ideal when tests/golden/patch_cost.json holds it)

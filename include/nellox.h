@@ -82,7 +82,7 @@ typedef struct {
                          symbols at once (with 16, every row of a 16-row group has
                          its own stream); -1 (wavefront order 1 only): one stream
                          per lane row, so every row of every step decodes at once,
-                         the lane in bands of 64 rows on as many CUs (meant for
+                         the lane in bands of 16 rows on as many CUs (meant for
                          whole-image lanes, the paper's exact method: a row of W
                          pixels costs one stream). Each stream costs its start
                          and flush, about 4.6 bits */
@@ -190,7 +190,7 @@ typedef struct {
   int64_t counter_offset;       /* byte offset of the lane-queue counter */
   int64_t ring_offset;          /* order 2: byte offset of the per-wave sheared context rings */
   int64_t ring_rows;            /* order 2: rows of a ring (tallest lane + h, padded) */
-  int64_t n_bands;              /* row streams: bands of 64 lane rows (the launch's work items) */
+  int64_t n_bands;              /* row streams: bands of 16 lane rows (the launch's work items) */
   int64_t progress_offset;      /* row streams: byte offset of the per-band progress counters */
 } nellox_decode_plan;
 

@@ -316,6 +316,121 @@ NXD void net_forward(const float* __restrict__ w, int nb, const float (&ctx)[con
   layer_mm<HEAD_TILES, MT>(w_head, u, head, lane);
 }
 
+// The network of one 16-pixel tile computed by the NW waves of a workgroup
+// together: wave wv computes the output tiles mt with mt % NW == wv of every
+// layer and the head tiles likewise, and the activations each 1x1 layer
+// reads are exchanged through LDS (xb: two buffers of C/16 tiles x 64 lanes x
+// 4 floats, used in turn), so every wave holds all input tiles. Each output
+// element is the chain of MFMAs net_forward computes for it, in the same k
+// order, so the values are bitwise the same. The head rows go to
+// hb[pixel * 128 + row] (the weight image's permuted row order). Every wave
+// of the workgroup must call it: it holds barriers, and its last one makes
+// hb readable by all.
+template <int H_, int C_, int NW>
+NXD void net_forward_split(const float* __restrict__ w, int nb, const float (&ctx)[conv_chunks(H_)], float* xb,
+                           float* hb, int lane, int wv) {
+  constexpr int MT = C_ / 16;
+  constexpr int KC = conv_chunks(H_), KQ = conv_quads(H_);
+  constexpr int MY = (MT + NW - 1) / NW;  // output tiles per wave (a wave may own none)
+  constexpr int HY = HEAD_TILES / NW;
+  static_assert(HEAD_TILES % NW == 0, "head tiles are dealt evenly");
+  const WeightLayout L = weight_layout(H_, C_, 0);
+  const int g = lane >> 4;
+  const int64_t layer_stride = (int64_t)MT * MT * 256;
+  const float* bias_conv = w + L.head + (int64_t)HEAD_TILES * MT * 256 + 2 * (int64_t)nb * layer_stride;
+  const float* bias_blk = bias_conv + C_;
+  const float* bias_head = bias_blk + 2 * (int64_t)nb * C_;
+  const float* w_head = w + L.layer0 + 2 * (int64_t)nb * layer_stride;
+
+  // out (pre-initialised with the bias) += W in for output tile mt of a
+  // layer (or of the head): k-chunks in the order (ct, q), as layer_mm
+  auto tile_mm = [&](const float* wl, const f4(&in)[MT], f4& out, int mt) {
+#pragma unroll
+    for (int ct = 0; ct < MT; ++ct) {
+      const f4 wq = *(const f4*)(wl + (((int64_t)mt * MT + ct) * 64 + lane) * 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], in[ct][q], out, 0, 0, 0);
+    }
+  };
+  int par = 0;
+  auto share = [&](const f4(&u)[MY], f4(&in)[MT]) {
+    float* X = xb + par * (MT * 256);
+#pragma unroll
+    for (int k = 0; k < MY; ++k) {
+      const int mt = wv + NW * k;
+      if (mt < MT) *(f4*)(X + ((int64_t)mt * 64 + lane) * 4) = u[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) in[mt] = *(const f4*)(X + ((int64_t)mt * 64 + lane) * 4);
+    par ^= 1;
+  };
+
+  f4 a[MY];
+#pragma unroll
+  for (int k = 0; k < MY; ++k) {
+    const int mt = wv + NW * k;
+    if (mt >= MT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[k][v] = bias_conv[16 * mt + 4 * g + v];
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+      const f4 wq = *(const f4*)(w + (((int64_t)mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * kq + q < KC) a[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], ctx[4 * kq + q], a[k], 0, 0, 0);
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    f4 u[MY], in[MT], z[MY];
+#pragma unroll
+    for (int k = 0; k < MY; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u[k][v] = xelu(a[k][v]);
+    share(u, in);
+#pragma unroll
+    for (int k = 0; k < MY; ++k) {
+      const int mt = wv + NW * k;
+      if (mt >= MT) continue;
+      const float* bb = bias_blk + (int64_t)(2 * b) * C_;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z[k][v] = bb[16 * mt + 4 * g + v];
+      tile_mm(w + L.layer0 + (int64_t)(2 * b) * layer_stride, in, z[k], mt);
+    }
+#pragma unroll
+    for (int k = 0; k < MY; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u[k][v] = xelu(z[k][v]);
+    share(u, in);
+#pragma unroll
+    for (int k = 0; k < MY; ++k) {
+      const int mt = wv + NW * k;
+      if (mt >= MT) continue;
+      const float* bb = bias_blk + (int64_t)(2 * b + 1) * C_;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z[k][v] = bb[16 * mt + 4 * g + v];
+      tile_mm(w + L.layer0 + (int64_t)(2 * b + 1) * layer_stride, in, z[k], mt);
+      a[k] = a[k] + z[k];
+    }
+  }
+  f4 u[MY], in[MT];
+#pragma unroll
+  for (int k = 0; k < MY; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[k][v] = xelu(a[k][v]);
+  share(u, in);
+#pragma unroll
+  for (int k = 0; k < HY; ++k) {
+    const int hm = wv + NW * k;
+    f4 hd;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) hd[v] = bias_head[16 * hm + 4 * g + v];
+    tile_mm(w_head, in, hd, hm);
+    *(f4*)(hb + (lane & 15) * 128 + 16 * hm + 4 * g) = hd;
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ mixture
 // Head slot s = 4 mt + v of lane group g holds parameter s % 10 of component
 // m = g + 4 (s / 10) (s < 30, m < 10): 0 logit, 1..3 means R,G,B,
@@ -438,6 +553,96 @@ NXD float posterior(Mix& M, int x, const float (&mu)[3], const float (&is)[3], b
   const float lse = lse10(t, has2);
 #pragma unroll
   for (int j = 0; j < 3; ++j) M.logw[j] = t[j] - lse;
+  return lse;
+}
+
+// ------------------------------------------------------------------ mixture, 16 lanes per pixel
+// The row decoder's mixture phase gives each pixel a row of 16 lanes: lane m
+// holds component m (m < 10; lanes 10..15 hold none and add nothing). The
+// arithmetic of a component is the lane-group form's, and sums over the
+// components take the same tree: lane g < 4 adds (t_g + t_{g+4}) + t_{g+8},
+// then (s_0 + s_1) + (s_2 + s_3), so every value is bitwise the one the
+// encoder and the other decoders compute. The tree runs on DPP row shifts
+// (lane i reads lane i + n of its row; only lanes 0..3 use the sums), and
+// row_newbcast hands lane 0's result to the whole row.
+template <int CTRL>
+NXD float dpp_row(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+constexpr int DPP_SHL1 = 0x101, DPP_SHL2 = 0x102, DPP_SHL4 = 0x104, DPP_SHL8 = 0x108, DPP_BCAST0 = 0x150;
+NXD float row_bcast0(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_BCAST0, 0xf, 0xf, false));
+}
+NXD float row16_sum(float t) {
+  const float s = (t + dpp_row<DPP_SHL4>(t)) + dpp_row<DPP_SHL8>(t);
+  const float u = s + dpp_row<DPP_SHL1>(s);
+  return row_bcast0(u + dpp_row<DPP_SHL2>(u));
+}
+NXD float row16_max(float v) {
+  v = fmaxf(v, dpp_row<DPP_SHL8>(v));
+  v = fmaxf(v, dpp_row<DPP_SHL4>(v));
+  v = fmaxf(v, dpp_row<DPP_SHL2>(v));
+  v = fmaxf(v, dpp_row<DPP_SHL1>(v));
+  return row_bcast0(v);
+}
+// lse10 over the row's live components (t of a lane without one is ignored)
+NXD float lse16(float t, bool live) {
+  const float m = row16_max(live ? t : -INFINITY);
+  const float e = live ? xexp(t - m) : 0.0f;
+  return m + xlog(row16_sum(e));
+}
+
+struct Mix16 {
+  float logw;                  // posterior log weight of this lane's component
+  float mu[3], invs[3], co[3];
+};
+// the weight image's head row of parameter k (0..9) of component m
+NXD int head_row(int m, int k) {
+  const int s = 10 * (m >> 2) + k;
+  return 16 * (s >> 2) + 4 * (m & 3) + (s & 3);
+}
+// mix_prep for component m of the pixel whose 128 head rows are at hp
+NXD void mix_prep16(const float* hp, int m, Mix16& M) {
+  const bool live = m < 10;
+  const int mm = live ? m : 0;
+  const float lam = live ? hp[head_row(mm, 0)] : -INFINITY;
+  M.logw = lam - lse16(lam, live);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    M.mu[c] = hp[head_row(mm, 1 + c)];
+    M.invs[c] = xexp(-fmaxf(hp[head_row(mm, 4 + c)], -7.0f));
+    M.co[c] = xtanh(hp[head_row(mm, 7 + c)]);
+  }
+}
+struct Chan16 {
+  float w, mu, is, a, b;
+};
+NXD void chan_params16(const Mix16& M, int c, float xr, float xg, Chan16& Q) {
+  Q.w = xexp(M.logw);
+  Q.is = c == 0 ? M.invs[0] : (c == 1 ? M.invs[1] : M.invs[2]);
+  float m;
+  if (c == 0) {
+    m = M.mu[0];
+  } else if (c == 1) {
+    m = M.mu[1] + M.co[0] * xr;
+  } else {
+    const float t1 = M.co[1] * xr;
+    const float t2 = M.co[2] * xg;
+    m = (M.mu[2] + t1) + t2;
+  }
+  Q.mu = m;
+  Q.a = Q.is * kLog2e;
+  Q.b = m * Q.a;
+}
+NXD float cdf_eval16(int k, const Chan16& Q) {
+  const float e = bin_edge(k);
+  const float x = __builtin_amdgcn_exp2f(__builtin_fmaf(-e, Q.a, Q.b));
+  return row16_sum(Q.w * __builtin_amdgcn_rcpf(1.0f + x));
+}
+NXD float posterior16(Mix16& M, int x, const Chan16& Q, bool live) {
+  const float t = live ? M.logw + log_bin(x, Q.mu, Q.is) : -INFINITY;
+  const float lse = lse16(t, live);
+  M.logw = t - lse;
   return lse;
 }
 

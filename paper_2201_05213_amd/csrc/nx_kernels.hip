@@ -733,6 +733,44 @@ NXD int pop_own(const Chan& Q, PixStream& P, bool act, uint32_t& start, uint32_t
   return lo;
 }
 
+// pop_own for the 16-lanes-per-pixel layout of the row decoder: the same
+// eight halvings, each one cdf_eval16 (bitwise the encoder's CDF value)
+NXD int pop16(const Chan16& Q, PixStream& P, bool act, uint32_t& start, uint32_t& freq) {
+  const uint32_t lm = P.len - 1u;
+  const uint32_t nb0 = P.S[min(P.pos, lm)];
+  const uint32_t nb1 = P.S[min(P.pos + 1u, lm)];
+  const bool small = P.x < CDF_TOTAL;
+  const uint32_t slot = small ? rev16(P.x) : (P.x & 0xffffu);
+  int lo = 0;
+  uint32_t clo = 0u, chi = CDF_TOTAL;
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int mid = lo + (128 >> it);
+    const uint32_t v = cdf_quant(mid, cdf_eval16(mid, Q));
+    const bool le = v <= slot;
+    lo = le ? mid : lo;
+    clo = le ? v : clo;
+    chi = le ? chi : v;
+  }
+  freq = chi - clo;
+  start = clo;
+  uint32_t xn = freq * (P.x >> 16) + slot - clo;
+  if (__ballot(small && act) != 0ull) {
+    const uint32_t xr = spread_rank(P.x, clo, freq);
+    xn = small ? xr : xn;
+  }
+  uint32_t pn = P.pos;
+  const bool r0 = xn < RANS_L && pn < P.len;
+  xn = r0 ? ((xn << 8) | nb0) : xn;
+  pn += r0 ? 1u : 0u;
+  const bool r1 = xn < RANS_L && pn < P.len;
+  xn = r1 ? ((xn << 8) | nb1) : xn;
+  pn += r1 ? 1u : 0u;
+  P.x = act ? xn : P.x;
+  P.pos = act ? pn : P.pos;
+  return lo;
+}
+
 // a stream's initial state: its first bytes, most significant first, read
 // while x < L (at most four; loads clamped into the stream, len >= 1)
 NXD void stream_begin(PixStream& P) {
@@ -1217,25 +1255,24 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
 
 // ------------------------------------------------------------------ row streams
 // Row streams (one rANS stream per lane row): a lane is decoded in bands of
-// ROW_BAND rows, one workgroup of ROW_WAVES waves per band. At wavefront step
-// t the band's rows of the step are cut into groups of 16, one per wave; each
-// row pops its own stream, so every row of a step decodes at once (the whole
-// step of Algorithm 1 in parallel). A row's coder state lives in LDS between
-// steps (rows move from wave to wave as the step's first row advances).
-// A band's top rows read the h rows above, decoded by the band above it,
-// possibly on another CU: each band publishes how many steps it has finished
-// (release), and waits before step t until the band above has finished step
-// t - 1 (acquire). Bands are taken from the queue in order, so the band above
-// is always held by a running workgroup; its skew of (h + 1) ROW_BAND steps
-// makes waits rare once a band has started. A wait also ends, with the image
-// marked corrupt, if it exceeds BAND_WAIT_TICKS of the 100 MHz clock, so
-// every workgroup reaches the end of the kernel whatever happens.
+// ROW_BAND = 16 rows, one workgroup of ROW_WAVES = 4 waves (one per SIMD) per
+// band, so one wavefront step of a band, up to 16 pixels, is shared by a whole
+// CU: the network is split by output tiles (net_forward_split, activations
+// exchanged through LDS), then each wave decodes four of the band's rows with
+// 16 lanes per pixel, one mixture component per lane. Each row pops its own
+// stream, so every row of a step decodes at once (the whole step of
+// Algorithm 1 in parallel); a row's coder state stays in the registers of
+// the lanes that decode it. A band's top rows read the h rows above, decoded
+// by the band above it, possibly on another CU: each band publishes how many
+// steps it has finished (release), and waits before step t until the band
+// above has finished step t - 1 (acquire). Bands are taken from the queue in
+// order, so the band above is always held by a running workgroup; its skew of
+// (h + 1) ROW_BAND steps makes waits rare once a band has started. A wait also
+// ends, with the image marked corrupt, if it exceeds BAND_WAIT_TICKS of the
+// 100 MHz clock, so every workgroup reaches the end of the kernel whatever
+// happens.
 constexpr int32_t BAND_DONE = 0x7fffffff;
 constexpr uint64_t BAND_WAIT_TICKS = 2000000000ull;  // 20 s
-
-struct RowState {
-  uint32_t x, pos, start, len;  // coder state, position, and the row stream's bytes in the payload
-};
 
 NXD int find_img_band(const ImgDesc* __restrict__ d, int n, int64_t key) {
   int lo = 0, hi = n - 1;
@@ -1252,10 +1289,11 @@ NXD void band_publish(int32_t* slot, int32_t v) {
 }
 
 template <int H_, int C_, bool TRACE>
-__device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int32_t* sh, int64_t B) {
+__device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* hb, int32_t* sh, int64_t B) {
+  static_assert(ROW_BAND == 16 && ROW_WAVES == 4, "a band is one 16-pixel tile, four rows per wave");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p = lane & 15, g = lane >> 4;
-  const bool has2 = g < 2;
+  const int p = lane & 15;                 // network phase: the tile's pixel p is band row p
+  const int m = lane & 15, pp = 4 * wave + (lane >> 4);  // mixture phase: component m of band row pp
   const int n = find_img_band(A.desc, A.n_img, B);
   const ImgDesc D = uniform_desc(A.desc + n);
   // which lane of the image and which band of it: lanes in order, full patch
@@ -1267,7 +1305,7 @@ __device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int3
   const int64_t rem = bi - (int64_t)ly * per_prow;
   const int lx = (int)(rem / bands_of(Hl)), bb = (int)(rem - (int64_t)lx * bands_of(Hl));
   const int x0 = lx * D.pw, Wl = min(D.pw, D.W - x0);
-  const int q = ly * D.nlx + lx, nl = D.nlx * D.nly;
+  const int nl = D.nlx * D.nly;
   const int r0 = bb * ROW_BAND, r1 = min(Hl, r0 + ROW_BAND) - 1, nrows = r1 - r0 + 1;
   int32_t* mine = A.progress + B;
   // header and stream table (every lane reads the same bytes)
@@ -1290,22 +1328,27 @@ __device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int3
       mismatch = uniform(hsh != A.model_hash ? 1 : 0) != 0;
     }
   }
-  // the band's rows: stream table entries, initial states
+  // this lane's row stream (band row pp; rows past the band's last take the
+  // last row's and never pop), in every lane of the row's pixel
   const int64_t ebase = row_entry_base(ly, lx, D.nlx, D.ph, Hl) + r0;
   if (threadIdx.x == 0) sh[0] = 1;
   __syncthreads();
+  PixStream P;
+  P.x = 0u;
+  P.pos = 0u;
+  P.len = 1u;
+  P.S = as_global(C);
   if (ok && !mismatch) {
-    for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
-      const int64_t e = ebase + k;
-      const uint32_t lend = rd_u32(C + HDR_BYTES + 4 * e);
-      const uint32_t lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
-      const bool okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
-      PixStream P;
-      P.S = as_global(C + pay + (okr ? lstart : 0u));
-      P.len = okr ? lend - lstart : 1u;
+    const int64_t e = ebase + min(pp, nrows - 1);
+    const uint32_t lend = rd_u32(C + HDR_BYTES + 4 * e);
+    const uint32_t lstart = e > 0 ? rd_u32(C + HDR_BYTES + 4 * (e - 1)) : 0u;
+    const bool okr = lstart <= lend && pay + (int64_t)lend <= clen && lend - lstart >= 1;
+    if (okr) {
+      P.S = as_global(C + pay + lstart);
+      P.len = lend - lstart;
       stream_begin(P);
-      rs[k] = RowState{P.x, P.pos, okr ? lstart : 0u, P.len};
-      if (!okr) sh[0] = 0;
+    } else {
+      sh[0] = 0;
     }
   }
   __syncthreads();
@@ -1323,7 +1366,7 @@ __device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int3
   const int t_lo = o * r0, t_hi = (Wl - 1) + o * r1;
   uint32_t* dump = TRACE ? A.sym_dump + D.px_base * 3 : nullptr;
   TapCodes<H_> tc;
-  tc.init(g);
+  tc.init(lane >> 4);
   int32_t seen = bb == 0 ? BAND_DONE : 0;  // steps of the band above known to be finished
   for (int t = t_lo; t <= t_hi; ++t) {
     if (seen < t) {
@@ -1347,69 +1390,70 @@ __device__ void decode_band(const DecArgs& A, const float* w, RowState* rs, int3
       __syncthreads();
       seen = sh[1];
     }
-    // this band's step t - 1 is finished in every wave (pixels, row states)
+    // this band's step t - 1 is finished in every wave (its pixels stored)
     __syncthreads();
     if (threadIdx.x == 0) band_publish(mine, t);
     int ilo, ihi;
     step_rows(t, Hl, Wl, o, ilo, ihi);
     const int a = max(ilo, r0), bmax = min(ihi, r1);
-    const int ts = a + 16 * wave;
-    if (ts > bmax) continue;
-    const int na = min(16, bmax - ts + 1);
-    const int i = ts + p;
-    const bool active = p < na;
+    if (a > bmax) continue;  // the same for the whole workgroup
+    // network: every wave gathers the tile's contexts, then computes its
+    // share of the layers
+    {
+      const int i = r0 + p;
+      const bool active = i >= a && i <= bmax;
+      float ctx[conv_chunks(H_)];
+      tc.refresh();
+      gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, t - o * i, active);
+      net_forward_split<H_, C_, ROW_WAVES>(lds_weights(w), A.nb, ctx, xb, hb, lane, wave);
+    }
+    // mixture and pops: band row pp, component m
+    const int i = r0 + pp;
+    const bool act = i >= a && i <= bmax;
     const int j = t - o * i;
-    float ctx[conv_chunks(H_)];
-    tc.refresh();
-    gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, j, active);
-    f4 head[HEAD_TILES];
-    net_forward<H_, C_>(lds_weights(w), A.nb, ctx, head, lane);
-    Mix M;
-    mix_prep(head, M, has2);
-    // the row's stream
-    const int k = min(i, bmax) - r0;
-    const RowState R = rs[k];
-    PixStream P;
-    P.S = as_global(C + pay + R.start);
-    P.len = R.len;
-    P.x = R.x;
-    P.pos = R.pos;
+    const bool live = m < 10;
+    Mix16 M;
+    mix_prep16(hb + pp * 128, m, M);
     int xv[3] = {0, 0, 0};
     float xr = 0.0f, xg = 0.0f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      Chan Q;
-      chan_params(M, c, xr, xg, Q);
+      Chan16 Q;
+      chan_params16(M, c, xr, xg, Q);
       uint32_t start, freq;
-      const int sy = pop_own(Q, P, active, start, freq);
+      const int sy = pop16(Q, P, act, start, freq);
       if (c == 0) xv[0] = sy;
       else if (c == 1) xv[1] = sy;
       else xv[2] = sy;
-      if (TRACE && active && g == 0)
+      if (TRACE && act && m == 0)
         dump[((int64_t)(y0 + i) * D.W + (x0 + j)) * 3 + c] = start | (freq << 16);
       if (c == 0) {
-        posterior(M, xv[0], Q.mu, Q.is, has2);
+        posterior16(M, xv[0], Q, live);
         xr = normalise(xv[0]);
       } else if (c == 1) {
-        posterior(M, xv[1], Q.mu, Q.is, has2);
+        posterior16(M, xv[1], Q, live);
         xg = normalise(xv[1]);
       }
     }
-    if (active && g == 0) {
+    if (act && m == 0) {
       uint8_t* dst = img + ((int64_t)(y0 + i) * D.W + (x0 + j)) * 3;
       dst[0] = (uint8_t)xv[0];
       dst[1] = (uint8_t)xv[1];
       dst[2] = (uint8_t)xv[2];
-      rs[k] = RowState{P.x, P.pos, R.start, R.len};
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) band_publish(mine, BAND_DONE);
   // every row's stream must end in the start state with every byte read
-  bool clean = true;
-  for (int k = threadIdx.x; k < nrows; k += blockDim.x) clean = clean && rs[k].x == RANS_X0 && rs[k].pos == rs[k].len;
-  if (!clean) A.status[n] = ST_CORRUPT;
+  if (pp < nrows && m == 0 && !(P.x == RANS_X0 && P.pos == P.len)) A.status[n] = ST_CORRUPT;
   __syncthreads();
+}
+
+// LDS of the row decoder after the weights: two activation exchange buffers
+// of C/16 tiles, the band's 16 x 128 head rows, then a few shared words
+template <int C_>
+constexpr size_t rows_lds_extra() {
+  return (size_t)(2 * (C_ / 16) * 256 + ROW_BAND * 128) * sizeof(float) + 4 * sizeof(int32_t);
 }
 
 template <int H_, int C_, bool TRACE>
@@ -1417,15 +1461,16 @@ __global__ void __launch_bounds__(ROW_WAVES * 64) k_decode_rows(DecArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
   load_weights(w, A.w, A.wfloats);
-  RowState* rs = (RowState*)(w + A.wfloats);
-  int32_t* sh = (int32_t*)(rs + ROW_BAND);  // band, wait and flag words shared by the workgroup
+  float* xb = w + A.wfloats;
+  float* hb = xb + 2 * (C_ / 16) * 256;
+  int32_t* sh = (int32_t*)(hb + ROW_BAND * 128);  // band, wait and flag words shared by the workgroup
   for (;;) {
     if (threadIdx.x == 0) sh[2] = atomicAdd(A.counter, 1);
     __syncthreads();
     const int64_t B = sh[2];
     __syncthreads();
     if (B >= A.n_bands) break;
-    decode_band<H_, C_, TRACE>(A, w, rs, sh, B);
+    decode_band<H_, C_, TRACE>(A, w, xb, hb, sh, B);
   }
 }
 
@@ -1691,7 +1736,7 @@ hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipS
 
 template <int H_, int C_>
 static hipError_t rows_t(const DecArgs& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.wfloats * 4 + ROW_BAND * sizeof(RowState) + 4 * sizeof(int32_t);
+  const size_t lds = (size_t)a.wfloats * 4 + rows_lds_extra<C_>();
   if (a.sym_dump)
     hipLaunchKernelGGL((k_decode_rows<H_, C_, true>), dim3(grid), dim3(ROW_WAVES * 64), lds, s, a);
   else

@@ -136,8 +136,8 @@ hipError_t launch_rans_encode(const RansEncArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipStream_t s,
                               int32_t* progress = nullptr, int64_t n_bands = 0);
-// row streams: the band decoder (ROW_BAND / 16 waves per workgroup, one band at a time)
-constexpr int ROW_WAVES = ROW_BAND / 16;
+// row streams: the band decoder (four waves per workgroup, one per SIMD, one band at a time)
+constexpr int ROW_WAVES = 4;
 hipError_t launch_decode_rows(int h, int C, const DecArgs& a, int grid, hipStream_t s);
 // raise the decoder kernels' LDS limit (once, outside any stream capture)
 hipError_t prepare_decode(int h, int C, int K);

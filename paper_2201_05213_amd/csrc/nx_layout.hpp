@@ -77,9 +77,9 @@ constexpr int ROW_STREAMS = 0;
 NXHD int64_t row_entry_base(int ly, int lx, int nlx, int ph, int Hl) {
   return (int64_t)ly * nlx * ph + (int64_t)lx * Hl;
 }
-// a lane's rows are decoded in bands of ROW_BAND rows, one workgroup of
-// ROW_BAND / 16 waves each, a band waiting on the progress of the one above
-constexpr int ROW_BAND = 64;
+// a lane's rows are decoded in bands of ROW_BAND rows (one 16-pixel tile),
+// one workgroup each, a band waiting on the progress of the one above
+constexpr int ROW_BAND = 16;
 NXHD int bands_of(int Hl) { return (Hl + ROW_BAND - 1) / ROW_BAND; }
 // streams and bands of an image of H rows with a grid of nlx x nly patches of ph rows
 NXHD int64_t image_streams(int K, int H, int nlx, int nly) {
