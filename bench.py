@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--no-trained", action="store_true",
                     help="skip the trained-model leg (model B after the 2000-step training recipe, trained on the "
                          "CPU by the oracle: decode time and the bits gap at about 4 bits/dim)")
+    ap.add_argument("--profile-rows", action="store_true",
+                    help="only decode image 0 (1024^2) as a whole-image lane with row streams, warmup + steps "
+                         "times (for profiler runs of the row-stream decoder; prints no JSON)")
     ap.add_argument("--profile", action="store_true",
                     help="time only the batch decode, then run the full-image pass and the encode three times "
                          "each and a known-size copy for counter calibration (for profiler runs; prints no "
@@ -171,6 +174,17 @@ def main():
         ph, pw = (int(v) for v in (args.patch.split("x") if "x" in args.patch else (args.patch, args.patch)))
     patch = (ph, pw)
     pname = f"{ph}x{pw}"
+    if args.profile_rows:
+        d0, o0 = m.encode([ts[0]], order=nx.WAVEFRONT, interleave=nx.ROWS)
+        out0 = [torch.empty_like(ts[0])]
+        plan0, ws0 = m.decode_prepare(out0, order=nx.WAVEFRONT, interleave=nx.ROWS)
+        st0 = torch.empty(1, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup + args.steps):
+            m.decode_run(plan0, d0, o0, st0, ws0)
+        torch.cuda.synchronize()
+        assert int(st0[0]) == 0 and torch.equal(out0[0], ts[0])
+        log(f"[bench] profile-rows mode: {args.warmup + args.steps} decodes of one 1024^2 image done")
+        return
     lanes_x = -(-1024 // pw)  # lanes across a 1024-wide image
 
     def lane_crop(img, q):

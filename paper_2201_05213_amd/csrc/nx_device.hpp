@@ -188,6 +188,42 @@ NXD void gather(float (&ctx)[conv_chunks(H_)], const TapCodes<H_>& tc, const uin
   }
 }
 
+// gather() shared by the NW waves of a workgroup that all need the same
+// tile's contexts: wave wv loads and normalises the K-chunks kc = wv, wv + NW,
+// ... (the same positions, clamps and masks as gather(), tap offsets computed
+// from the chunk index), writes them to LDS (cb: 64 lanes x gather_stride
+// floats), and after a barrier every wave reads all of them. Every wave of
+// the workgroup must call it.
+template <int H_>
+constexpr int gather_stride() { return (conv_chunks(H_) + 3) / 4 * 4; }
+template <int H_, int NW>
+NXD void gather_shared(float (&ctx)[conv_chunks(H_)], const uint8_t* img, int W, int y0, int x0, int Hl, int Wl,
+                       int i, int j, bool active, int wv, float* cb, int lane) {
+  constexpr int KC = conv_chunks(H_), KW = 2 * H_ + 1, CS = gather_stride<H_>();
+  const int g = lane >> 4;
+  const gbytes gimg = as_global(img);
+  float v[(KC + NW - 1) / NW];
+#pragma unroll
+  for (int k = 0; k < (KC + NW - 1) / NW; ++k) {
+    const int kc = min(wv + NW * k, KC - 1);
+    const int kk = 4 * kc + g, tap = kk / 3, ch = kk - 3 * tap;
+    const int dy = tap < H_ * KW ? tap / KW : H_;
+    const int dx = tap < H_ * KW ? tap - KW * dy : tap - H_ * KW;
+    const int y = i - H_ + dy, x = j - H_ + dx;
+    const int yc = min(max(y, 0), Hl - 1), xc = min(max(x, 0), Wl - 1);
+    const uint32_t raw = gimg[((int64_t)(y0 + yc) * W + (x0 + xc)) * 3 + ch];
+    const int ok = -(int)(((unsigned)y < (unsigned)Hl) & ((unsigned)x < (unsigned)Wl) & (unsigned)active);
+    const int num = (2 * (int)raw - 255) & ok;
+    v[k] = (float)num * (1.0f / 255.0f);
+  }
+#pragma unroll
+  for (int k = 0; k < (KC + NW - 1) / NW; ++k)
+    if (wv + NW * k < KC) cb[lane * CS + wv + NW * k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) ctx[kc] = cb[lane * CS + kc];
+}
+
 // Context of pixel (i, t) of a lane from its sheared canvas window (Sec. 3.1,
 // Algorithm 2): tap (dy, dx) of the causal kernel is row i - h + dy, sheared
 // column t - h(h+2) + (h+1) dy + dx, always a column before t. The window
@@ -344,13 +380,16 @@ NXD void net_forward_split(const float* __restrict__ w, int nb, const float (&ct
 
   // out (pre-initialised with the bias) += W in for output tile mt of a
   // layer (or of the head): k-chunks in the order (ct, q), as layer_mm
+  // (a wave's tile is one dependent MFMA chain, so the layer's weights are
+  // all read from LDS before the chain starts)
   auto tile_mm = [&](const float* wl, const f4(&in)[MT], f4& out, int mt) {
+    f4 wq[MT];
 #pragma unroll
-    for (int ct = 0; ct < MT; ++ct) {
-      const f4 wq = *(const f4*)(wl + (((int64_t)mt * MT + ct) * 64 + lane) * 4);
+    for (int ct = 0; ct < MT; ++ct) wq[ct] = *(const f4*)(wl + (((int64_t)mt * MT + ct) * 64 + lane) * 4);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) out = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], in[ct][q], out, 0, 0, 0);
-    }
+    for (int ct = 0; ct < MT; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[ct][q], in[ct][q], out, 0, 0, 0);
   };
   int par = 0;
   auto share = [&](const f4(&u)[MY], f4(&in)[MT]) {
@@ -373,13 +412,14 @@ NXD void net_forward_split(const float* __restrict__ w, int nb, const float (&ct
     if (mt >= MT) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) a[k][v] = bias_conv[16 * mt + 4 * g + v];
+    f4 wq[KQ];
 #pragma unroll
-    for (int kq = 0; kq < KQ; ++kq) {
-      const f4 wq = *(const f4*)(w + (((int64_t)mt * KQ + kq) * 64 + lane) * 4);
+    for (int kq = 0; kq < KQ; ++kq) wq[kq] = *(const f4*)(w + (((int64_t)mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (4 * kq + q < KC) a[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[q], ctx[4 * kq + q], a[k], 0, 0, 0);
-    }
+        if (4 * kq + q < KC) a[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(wq[kq][q], ctx[4 * kq + q], a[k], 0, 0, 0);
   }
   for (int b = 0; b < nb; ++b) {
     f4 u[MY], in[MT], z[MY];

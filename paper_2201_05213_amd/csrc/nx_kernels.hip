@@ -733,8 +733,13 @@ NXD int pop_own(const Chan& Q, PixStream& P, bool act, uint32_t& start, uint32_t
   return lo;
 }
 
-// pop_own for the 16-lanes-per-pixel layout of the row decoder: the same
-// eight halvings, each one cdf_eval16 (bitwise the encoder's CDF value)
+// pop_own for the 16-lanes-per-pixel layout of the row decoder. A wave has
+// its SIMD to itself here, so the search trades instructions for a shorter
+// dependent chain: four quarterings of [0, 256) instead of eight halvings,
+// the three quartile points of a step evaluated together (cdf_eval16,
+// bitwise the encoder's CDF values; the CDF is increasing, so the points at
+// or below the slot are a prefix). The bracket found, and its CDF values,
+// are the bisection's.
 NXD int pop16(const Chan16& Q, PixStream& P, bool act, uint32_t& start, uint32_t& freq) {
   const uint32_t lm = P.len - 1u;
   const uint32_t nb0 = P.S[min(P.pos, lm)];
@@ -744,13 +749,16 @@ NXD int pop16(const Chan16& Q, PixStream& P, bool act, uint32_t& start, uint32_t
   int lo = 0;
   uint32_t clo = 0u, chi = CDF_TOTAL;
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int mid = lo + (128 >> it);
-    const uint32_t v = cdf_quant(mid, cdf_eval16(mid, Q));
-    const bool le = v <= slot;
-    lo = le ? mid : lo;
-    clo = le ? v : clo;
-    chi = le ? chi : v;
+  for (int st = 0; st < 4; ++st) {
+    const int d = 64 >> (2 * st);
+    const int k1 = lo + d, k2 = lo + 2 * d, k3 = lo + 3 * d;
+    const uint32_t v1 = cdf_quant(k1, cdf_eval16(k1, Q));
+    const uint32_t v2 = cdf_quant(k2, cdf_eval16(k2, Q));
+    const uint32_t v3 = cdf_quant(k3, cdf_eval16(k3, Q));
+    const bool l1 = v1 <= slot, l2 = v2 <= slot, l3 = v3 <= slot;
+    lo = l3 ? k3 : (l2 ? k2 : (l1 ? k1 : lo));
+    clo = l3 ? v3 : (l2 ? v2 : (l1 ? v1 : clo));
+    chi = l3 ? chi : (l2 ? v3 : (l1 ? v2 : v1));
   }
   freq = chi - clo;
   start = clo;
@@ -1289,7 +1297,8 @@ NXD void band_publish(int32_t* slot, int32_t v) {
 }
 
 template <int H_, int C_, bool TRACE>
-__device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* hb, int32_t* sh, int64_t B) {
+__device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* hb, float* cb, int32_t* sh,
+                            int64_t B) {
   static_assert(ROW_BAND == 16 && ROW_WAVES == 4, "a band is one 16-pixel tile, four rows per wave");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15;                 // network phase: the tile's pixel p is band row p
@@ -1365,8 +1374,6 @@ __device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* 
   const int o = H_ + 1;
   const int t_lo = o * r0, t_hi = (Wl - 1) + o * r1;
   uint32_t* dump = TRACE ? A.sym_dump + D.px_base * 3 : nullptr;
-  TapCodes<H_> tc;
-  tc.init(lane >> 4);
   int32_t seen = bb == 0 ? BAND_DONE : 0;  // steps of the band above known to be finished
   for (int t = t_lo; t <= t_hi; ++t) {
     if (seen < t) {
@@ -1397,14 +1404,13 @@ __device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* 
     step_rows(t, Hl, Wl, o, ilo, ihi);
     const int a = max(ilo, r0), bmax = min(ihi, r1);
     if (a > bmax) continue;  // the same for the whole workgroup
-    // network: every wave gathers the tile's contexts, then computes its
-    // share of the layers
+    // network: the waves gather a share of the tile's contexts each, then
+    // compute their share of the layers
     {
       const int i = r0 + p;
       const bool active = i >= a && i <= bmax;
       float ctx[conv_chunks(H_)];
-      tc.refresh();
-      gather<H_>(ctx, tc, img, D.W, y0, x0, Hl, Wl, i, t - o * i, active);
+      gather_shared<H_, ROW_WAVES>(ctx, img, D.W, y0, x0, Hl, Wl, i, t - o * i, active, wave, cb, lane);
       net_forward_split<H_, C_, ROW_WAVES>(lds_weights(w), A.nb, ctx, xb, hb, lane, wave);
     }
     // mixture and pops: band row pp, component m
@@ -1450,10 +1456,12 @@ __device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* 
 }
 
 // LDS of the row decoder after the weights: two activation exchange buffers
-// of C/16 tiles, the band's 16 x 128 head rows, then a few shared words
-template <int C_>
+// of C/16 tiles, the band's 16 x 128 head rows, the tile's contexts (64 lanes
+// x gather_stride), then a few shared words
+template <int H_, int C_>
 constexpr size_t rows_lds_extra() {
-  return (size_t)(2 * (C_ / 16) * 256 + ROW_BAND * 128) * sizeof(float) + 4 * sizeof(int32_t);
+  return (size_t)(2 * (C_ / 16) * 256 + ROW_BAND * 128 + 64 * gather_stride<H_>()) * sizeof(float) +
+         4 * sizeof(int32_t);
 }
 
 template <int H_, int C_, bool TRACE>
@@ -1463,14 +1471,15 @@ __global__ void __launch_bounds__(ROW_WAVES * 64) k_decode_rows(DecArgs A) {
   load_weights(w, A.w, A.wfloats);
   float* xb = w + A.wfloats;
   float* hb = xb + 2 * (C_ / 16) * 256;
-  int32_t* sh = (int32_t*)(hb + ROW_BAND * 128);  // band, wait and flag words shared by the workgroup
+  float* cb = hb + ROW_BAND * 128;
+  int32_t* sh = (int32_t*)(cb + 64 * gather_stride<H_>());  // band, wait and flag words shared by the workgroup
   for (;;) {
     if (threadIdx.x == 0) sh[2] = atomicAdd(A.counter, 1);
     __syncthreads();
     const int64_t B = sh[2];
     __syncthreads();
     if (B >= A.n_bands) break;
-    decode_band<H_, C_, TRACE>(A, w, xb, hb, sh, B);
+    decode_band<H_, C_, TRACE>(A, w, xb, hb, cb, sh, B);
   }
 }
 
@@ -1736,7 +1745,7 @@ hipError_t launch_decode_prep(int32_t* status, int n_img, int32_t* counter, hipS
 
 template <int H_, int C_>
 static hipError_t rows_t(const DecArgs& a, int grid, hipStream_t s) {
-  const size_t lds = (size_t)a.wfloats * 4 + rows_lds_extra<C_>();
+  const size_t lds = (size_t)a.wfloats * 4 + rows_lds_extra<H_, C_>();
   if (a.sym_dump)
     hipLaunchKernelGGL((k_decode_rows<H_, C_, true>), dim3(grid), dim3(ROW_WAVES * 64), lds, s, a);
   else
