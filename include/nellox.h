@@ -246,6 +246,14 @@ nellox_status nellox_debug_cdf(const nellox_model* m, const nellox_image* img, c
  * counts: 4 device uint64. */
 nellox_status nellox_debug_check_monotone(uint64_t* counts, void* stream);
 
+/* For tests of the row-stream decoder's failure path: sets how long (in
+ * ticks of the 100 MHz clock) a band of rows may wait for the band above it
+ * in decodes launched from now on; a band that waits longer marks its image
+ * CORRUPT and finishes. ticks = 0 restores the default, 2e9 (20 s). Returns
+ * the previous limit. Process-wide; not for use while other threads launch
+ * decodes. */
+uint64_t nellox_debug_band_wait(uint64_t ticks);
+
 /* ---- training (the objective of Eq. 2: the model's code length, and its
  * gradient; Sec. 2.1 model) ----
  * These calls take the parameters directly instead of a model handle, so an

@@ -51,6 +51,7 @@ SIGNATURES = {
     "nellox_debug_symbols": (_ST, [_P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_cdf": (_ST, [_P, _P, _P, _P, _P, _SZ, _P]),
     "nellox_debug_check_monotone": (_ST, [_P, _P]),
+    "nellox_debug_band_wait": (ctypes.c_uint64, [ctypes.c_uint64]),
     "nellox_param_count": (ctypes.c_int64, [_P]),
     "nellox_train_workspace_bytes": (_SZ, [_P, _I32, _I32, _I32]),
     "nellox_nll_fwd_train": (_ST, [_P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -50,6 +51,8 @@ int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 // pinned plan staging allocated with the model, so that the no-allocation
 // decoder never has to grow it: descriptors of up to 2,730 images
 constexpr size_t STAGING_BYTES = (size_t)256 << 10;
+// the row decoder's wait limit for launches from now on (nellox_debug_band_wait)
+std::atomic<uint64_t> g_band_wait{BAND_WAIT_TICKS};
 
 }  // namespace
 
@@ -629,6 +632,7 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   a.ring_rows = (int)plan->ring_rows;
   a.progress = progress;
   a.n_bands = plan->n_bands;
+  a.band_wait_ticks = g_band_wait.load();
   if (rows) {
     a.K = ROW_STREAMS;
     e = launch_decode_rows(m->h, m->Cp, a, plan->grid, s);
@@ -786,6 +790,8 @@ nellox_status nellox_debug_symbols(const nellox_model* mc, int32_t n, const nell
   }
   return NELLOX_OK;
 }
+
+uint64_t nellox_debug_band_wait(uint64_t ticks) { return g_band_wait.exchange(ticks ? ticks : BAND_WAIT_TICKS); }
 
 nellox_status nellox_debug_check_monotone(uint64_t* counts, void* stream) {
   if (!counts) return fail(NELLOX_E_ARG, "counts is null");

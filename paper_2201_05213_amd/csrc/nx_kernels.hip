@@ -1276,11 +1276,10 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
 // above has finished step t - 1 (acquire). Bands are taken from the queue in
 // order, so the band above is always held by a running workgroup; its skew of
 // (h + 1) ROW_BAND steps makes waits rare once a band has started. A wait also
-// ends, with the image marked corrupt, if it exceeds BAND_WAIT_TICKS of the
-// 100 MHz clock, so every workgroup reaches the end of the kernel whatever
-// happens.
+// ends, with the image marked corrupt, if it exceeds band_wait_ticks of the
+// 100 MHz clock (20 s unless a test lowers it), so every workgroup reaches
+// the end of the kernel whatever happens.
 constexpr int32_t BAND_DONE = 0x7fffffff;
-constexpr uint64_t BAND_WAIT_TICKS = 2000000000ull;  // 20 s
 
 NXD int find_img_band(const ImgDesc* __restrict__ d, int n, int64_t key) {
   int lo = 0, hi = n - 1;
@@ -1386,7 +1385,7 @@ __device__ void decode_band(const DecArgs& A, const float* w, float* xb, float* 
           while (v < t) {
             __builtin_amdgcn_s_sleep(4);
             v = __hip_atomic_load(above, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            if (v < t && __builtin_amdgcn_s_memrealtime() - t0 > BAND_WAIT_TICKS) {
+            if (v < t && __builtin_amdgcn_s_memrealtime() - t0 > A.band_wait_ticks) {
               A.status[n] = ST_CORRUPT;  // never expected: the image cannot be trusted
               v = BAND_DONE;
             }

@@ -82,7 +82,11 @@ struct DecArgs {
   int ring_rows;
   int32_t* progress;       // row streams: per band, the steps it has finished (zeroed by the prep)
   int64_t n_bands;         // row streams: bands of the batch (the queue's work items)
+  uint64_t band_wait_ticks;  // row streams: the longest wait on the band above (100 MHz clock ticks)
 };
+// row streams: the default limit of a band's wait on the band above (20 s);
+// a wait that exceeds it marks the image corrupt and lets the band finish
+constexpr uint64_t BAND_WAIT_TICKS = 2000000000ull;
 
 // Training objective and gradient (nx_train.hip). n images of H x W, all
 // pixel tensors pixel-major.

@@ -189,3 +189,25 @@ def test_whole_1024_image(models, nx):
     torch.cuda.synchronize()
     assert int(st[0]) == 0 and torch.equal(out, t)
     say(f"[gpu] whole 1024^2 image, row streams: {e0.elapsed_time(e1):.1f} ms")
+
+
+def test_band_wait_limit_ends_the_wait(models, nx):
+    """The bounded wait on the band above, forced from the host: with a limit
+    of one clock tick every band that has to wait gives up at once, marks its
+    image corrupt and still finishes (the launch returns); with the default
+    limit restored the same container decodes exactly."""
+    m, _ = models["C"]
+    L = nx.load()
+    img = synth.smooth_field_image(2.0, 3, 2, 300, 120, 8500)
+    t = cuda(img)
+    data, offs = m.encode([t], order=nx.WAVEFRONT, interleave=nx.ROWS)
+    prev = L.nellox_debug_band_wait(1)
+    try:
+        _, st = m.decode(data, offs, [(300, 120)], order=nx.WAVEFRONT, interleave=nx.ROWS, sync=False)
+        torch.cuda.synchronize()
+        assert int(st[0]) == 4
+    finally:
+        L.nellox_debug_band_wait(0)
+    assert prev == 2_000_000_000
+    (out,), st = m.decode(data, offs, [(300, 120)], order=nx.WAVEFRONT, interleave=nx.ROWS)
+    assert int(st[0]) == 0 and torch.equal(out, t)
