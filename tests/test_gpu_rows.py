@@ -211,3 +211,53 @@ def test_band_wait_limit_ends_the_wait(models, nx):
     assert prev == 2_000_000_000
     (out,), st = m.decode(data, offs, [(300, 120)], order=nx.WAVEFRONT, interleave=nx.ROWS)
     assert int(st[0]) == 0 and torch.equal(out, t)
+
+
+def test_graph_capture_and_replay(models, nx):
+    """A prepared row-stream decode captured in a graph (the prep kernel
+    clears the band counters, no memset): every replay, with eager work in
+    between, decodes exactly, also after other containers of the same shapes
+    are copied into the captured input buffers."""
+    say("[gpu] row streams, graph capture of a prepared decode")
+    m, _ = models["B"]
+    shapes = [(150, 90), (40, 200), (33, 17)]
+    imgs = [synth.smooth_field_image(2.0, 3, 2, H, W, 8600 + k) for k, (H, W) in enumerate(shapes)]
+    ts = [cuda(i) for i in imgs]
+    ts2 = [cuda(np.ascontiguousarray(i[::-1, ::-1])) for i in imgs]
+    d1, o1 = m.encode(ts, order=nx.WAVEFRONT, interleave=nx.ROWS)
+    d2, o2 = m.encode(ts2, order=nx.WAVEFRONT, interleave=nx.ROWS)
+    buf = torch.zeros(max(d1.numel(), d2.numel()), dtype=torch.uint8, device="cuda")
+    offs = torch.zeros_like(o1)
+    buf[:d1.numel()].copy_(d1)
+    offs.copy_(o1)
+    outs = [torch.zeros_like(t) for t in ts]
+    plan, ws = m.decode_prepare(outs, order=nx.WAVEFRONT, interleave=nx.ROWS)
+    status = torch.full((len(ts),), 7, dtype=torch.int32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        m.decode_run(plan, buf, offs, status, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        m.decode_run(plan, buf, offs, status, ws)
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        status.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.abs().sum()) == 0, rep
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts)), rep
+    buf[:d2.numel()].copy_(d2)
+    offs.copy_(o2)
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.abs().sum()) == 0
+        assert all(torch.equal(a, b) for a, b in zip(outs, ts2))
