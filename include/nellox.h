@@ -192,6 +192,7 @@ typedef struct {
   int64_t ring_rows;            /* order 2: rows of a ring (tallest lane + h, padded) */
   int64_t n_bands;              /* row streams: bands of 16 lane rows (the launch's work items) */
   int64_t progress_offset;      /* row streams: byte offset of the per-band progress counters */
+  int64_t band_order_offset;    /* row streams: byte offset of the bands' queue order (0: image order) */
 } nellox_decode_plan;
 
 nellox_status nellox_decode_prepare(const nellox_model* m, int32_t n, const nellox_image* out,

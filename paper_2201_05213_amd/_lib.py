@@ -26,7 +26,8 @@ class NelloxDecodePlan(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_lanes", ctypes.c_int64),
                 ("model_hash", ctypes.c_uint64), ("ws_bytes", ctypes.c_int64), ("desc_offset", ctypes.c_int64),
                 ("counter_offset", ctypes.c_int64), ("ring_offset", ctypes.c_int64), ("ring_rows", ctypes.c_int64),
-                ("n_bands", ctypes.c_int64), ("progress_offset", ctypes.c_int64)]
+                ("n_bands", ctypes.c_int64), ("progress_offset", ctypes.c_int64),
+                ("band_order_offset", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)

@@ -114,6 +114,9 @@ struct Plan {
   int64_t rev_words = 0;    // encoder: coding-order symbol words of all streams
   int64_t after_words = 0;  // encoder: per-step offset entries of all streams
   int64_t max_lane_px = 0;
+  // row streams, decoding: the queue order of the bands (band_queue), kept
+  // only if it fits the staging buffer beside the descriptors
+  std::vector<int32_t> band_order;
 };
 
 // the coded order of a request: the sheared layout codes the wavefront order
@@ -177,6 +180,37 @@ nellox_status make_plan(int32_t n, const nellox_image* imgs, const nellox_opts* 
   return NELLOX_OK;
 }
 
+// Row streams: the bands of a batch in the order of the wavefront step they
+// start at (band bb of a lane starts at step (h + 1) ROW_BAND bb): the bb-th
+// band of every lane before any (bb + 1)-th, lanes in image and lane order.
+// Each entry is the band's index in image order (band_base, then lanes in
+// order, a lane's bands in order), which is what the kernel decomposes. A
+// band's upper neighbour comes earlier, so it is always held by a running
+// or finished workgroup; and the bands that may run at a time are taken
+// together, so an image that comes late in the batch does not wait for the
+// CUs of the images before it.
+std::vector<int32_t> band_queue(const Plan& P) {
+  std::vector<int32_t> q;
+  q.reserve((size_t)P.n_bands);
+  int max_b = 0;
+  for (const ImgDesc& D : P.d) max_b = std::max(max_b, bands_of(D.ph));
+  for (int bb = 0; bb < max_b; ++bb)
+    for (const ImgDesc& D : P.d)
+      for (int ly = 0; ly < D.nly; ++ly) {
+        const int Hl = std::min(D.ph, D.H - ly * D.ph), nb = bands_of(Hl);
+        if (nb <= bb) continue;
+        for (int lx = 0; lx < D.nlx; ++lx)
+          q.push_back((int32_t)(D.band_base + (int64_t)ly * D.nlx * bands_of(D.ph) + (int64_t)lx * nb + bb));
+      }
+  return q;
+}
+
+// descriptors, then (row streams) the band order, in one upload
+int64_t desc_bytes(const Plan& P, int n) {
+  const int64_t d = ((int64_t)sizeof(ImgDesc) * std::max(n, 1) + 15) & ~(int64_t)15;
+  return d + (P.K == ROW_STREAMS ? 4 * P.n_bands : 0);
+}
+
 // Workspace segments: first those of decoding, sampling, the NLL and the
 // debug calls (descriptors, queue counter, sheared windows, per-pixel bits,
 // partial sums, row-stream band progress; `small` bytes), then the
@@ -190,7 +224,7 @@ struct WsLayout {
 WsLayout ws_layout(const Plan& P, int n) {
   WsLayout W{};
   int64_t o = 0;
-  W.desc = o; o = align256(o + (int64_t)sizeof(ImgDesc) * std::max(n, 1));
+  W.desc = o; o = align256(o + desc_bytes(P, n));
   W.flags = o; o = align256(o + 64);
   W.ring = o; o = align256(o + P.ring_waves * ring_wave_bytes(P.ring_rows));
   W.bits = o; o = align256(o + 4 * std::max<int64_t>(P.n_px, 1));
@@ -240,7 +274,16 @@ void plan_ring(const nellox_model* m, Plan& P) {
 // upload the plan; fills the PassArgs common fields
 nellox_status upload_plan(nellox_model* m, const Plan& P, uint8_t* ws, const WsLayout& W, hipStream_t s) {
   if (P.d.empty()) return NELLOX_OK;
-  hipError_t e = stage_copy(m, ws + W.desc, P.d.data(), sizeof(ImgDesc) * P.d.size(), s);
+  hipError_t e;
+  if (P.band_order.empty()) {
+    e = stage_copy(m, ws + W.desc, P.d.data(), sizeof(ImgDesc) * P.d.size(), s);
+  } else {
+    const int64_t off = desc_bytes(P, (int)P.d.size()) - 4 * P.n_bands;
+    std::vector<uint8_t> buf((size_t)desc_bytes(P, (int)P.d.size()), 0);
+    memcpy(buf.data(), P.d.data(), sizeof(ImgDesc) * P.d.size());
+    memcpy(buf.data() + off, P.band_order.data(), 4 * P.band_order.size());
+    e = stage_copy(m, ws + W.desc, buf.data(), buf.size(), s);
+  }
   if (e != hipSuccess) return hip_fail(e, "plan upload");
   return NELLOX_OK;
 }
@@ -562,6 +605,9 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   if (n > 0 && !ws) return fail(NELLOX_E_ARG, "null workspace");
   const WsLayout W = ws_layout(P, n);
   if ((int64_t)ws_bytes < W.small) return fail(NELLOX_E_CAPACITY, "workspace too small");
+  // row streams: the bands in start-step order, if they fit one upload with
+  // the descriptors (else the bands are taken in image order)
+  if (P.K == ROW_STREAMS && n > 0 && desc_bytes(P, n) <= (int64_t)STAGING_BYTES) P.band_order = band_queue(P);
   hipStream_t s = (hipStream_t)stream;
   if (n > 0 && (st = upload_plan(m, P, (uint8_t*)ws, W, s))) return st;
   int grid = 0, waves = 0;
@@ -578,6 +624,7 @@ static nellox_status prepare_impl(nellox_model* m, int32_t n, const nellox_image
   plan->interleave = P.K == ROW_STREAMS ? -1 : P.K;
   plan->n_bands = P.n_bands;
   plan->progress_offset = W.progress;
+  plan->band_order_offset = P.band_order.empty() ? 0 : W.desc + desc_bytes(P, n) - 4 * P.n_bands;
   plan->waves = std::max(waves, 1);
   plan->grid = grid;
   plan->ring_offset = W.ring;
@@ -599,7 +646,9 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   if (!plan || plan->model_hash != m->hash || plan->n < 0 || plan->waves < 1 || plan->waves > DECODE_WAVES ||
       (!rows && !valid_interleave(plan->interleave)) || plan->order < 0 || plan->order > 2 ||
       (rows && (plan->order != 1 || plan->waves != ROW_WAVES || plan->n_bands < 0 ||
-                plan->progress_offset + 4 * plan->n_bands > plan->ws_bytes)) ||
+                plan->progress_offset + 4 * plan->n_bands > plan->ws_bytes ||
+                (plan->band_order_offset != 0 && (plan->band_order_offset < plan->desc_offset ||
+                                                  plan->band_order_offset + 4 * plan->n_bands > plan->ws_bytes)))) ||
       (plan->order == 2 && plan->n_lanes > 0 &&
        (ring_windows(plan->grid, plan->waves) * ring_wave_bytes(plan->ring_rows) > plan->ws_bytes ||
         plan->ring_rows < 4)))
@@ -632,6 +681,7 @@ static nellox_status run_impl(nellox_model* m, const nellox_decode_plan* plan, c
   a.ring_rows = (int)plan->ring_rows;
   a.progress = progress;
   a.n_bands = plan->n_bands;
+  a.band_order = rows && plan->band_order_offset ? (const int32_t*)(w8 + plan->band_order_offset) : nullptr;
   a.band_wait_ticks = g_band_wait.load();
   if (rows) {
     a.K = ROW_STREAMS;

@@ -1274,7 +1274,8 @@ __global__ void __launch_bounds__(NWAVES_DEC * 64) k_decode(DecArgs A) {
 // by the band above it, possibly on another CU: each band publishes how many
 // steps it has finished (release), and waits before step t until the band
 // above has finished step t - 1 (acquire). Bands are taken from the queue in
-// order, so the band above is always held by a running workgroup; its skew of
+// order (by the step they start at, across the images of the batch), so the
+// band above is always held by a running or finished workgroup; its skew of
 // (h + 1) ROW_BAND steps makes waits rare once a band has started. A wait also
 // ends, with the image marked corrupt, if it exceeds band_wait_ticks of the
 // 100 MHz clock (20 s unless a test lowers it), so every workgroup reaches
@@ -1475,9 +1476,11 @@ __global__ void __launch_bounds__(ROW_WAVES * 64) k_decode_rows(DecArgs A) {
   for (;;) {
     if (threadIdx.x == 0) sh[2] = atomicAdd(A.counter, 1);
     __syncthreads();
-    const int64_t B = sh[2];
+    const int64_t Q = sh[2];
     __syncthreads();
-    if (B >= A.n_bands) break;
+    if (Q >= A.n_bands) break;
+    // the queue's order of the bands (start step, then image and lane), or image order
+    const int64_t B = A.band_order ? (int64_t)uniform(A.band_order[Q]) : Q;
     decode_band<H_, C_, TRACE>(A, w, xb, hb, cb, sh, B);
   }
 }

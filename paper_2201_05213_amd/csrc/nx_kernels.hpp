@@ -83,6 +83,7 @@ struct DecArgs {
   int32_t* progress;       // row streams: per band, the steps it has finished (zeroed by the prep)
   int64_t n_bands;         // row streams: bands of the batch (the queue's work items)
   uint64_t band_wait_ticks;  // row streams: the longest wait on the band above (100 MHz clock ticks)
+  const int32_t* band_order; // row streams, nullable: queue position -> band (in image order)
 };
 // row streams: the default limit of a band's wait on the band above (20 s);
 // a wait that exceeds it marks the image corrupt and lets the band finish

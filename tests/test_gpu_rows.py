@@ -155,6 +155,10 @@ def test_prepared_runs_and_static_decode(models, nx):
     outs = [torch.zeros_like(x) for x in ts]
     plan, ws = m.decode_prepare(outs, order=nx.WAVEFRONT, interleave=nx.ROWS)
     assert plan.n_bands == 10 + 3  # bands of 16 rows
+    # the queue takes the bands by the step they start at: the first band of
+    # both images, then the second of both, ...
+    order = ws[plan.band_order_offset:plan.band_order_offset + 4 * plan.n_bands].cpu().numpy().view("<i4")
+    assert order.tolist() == [0, 10, 1, 11, 2, 12, 3, 4, 5, 6, 7, 8, 9]
     st = torch.empty(2, dtype=torch.int32, device="cuda")
     for _ in range(2):
         for o in outs:
@@ -261,3 +265,41 @@ def test_graph_capture_and_replay(models, nx):
         torch.cuda.synchronize()
         assert int(status.abs().sum()) == 0
         assert all(torch.equal(a, b) for a, b in zip(outs, ts2))
+
+
+def test_band_queue_order_with_patches(models, nx):
+    """The band order of a batch with patch grids (ragged patch rows, lanes
+    of different band counts): a permutation of the bands in which every
+    band comes after the one above it in its lane, ordered by band index
+    within the lane, then by image and lane (checked against an independent
+    enumeration); the batch decodes exactly in that order."""
+    m, _ = models["A"]
+    shapes = [(100, 70), (37, 50), (70, 33)]
+    patch = (40, 32)
+    imgs = [synth.smooth_field_image(2.0, 3, 2, H, W, 8700 + k) for k, (H, W) in enumerate(shapes)]
+    ts = [cuda(i) for i in imgs]
+    data, offs = m.encode(ts, order=nx.WAVEFRONT, patch=patch, interleave=nx.ROWS)
+    outs = [torch.zeros_like(t) for t in ts]
+    plan, ws = m.decode_prepare(outs, order=nx.WAVEFRONT, patch=patch, interleave=nx.ROWS)
+    # bands in image order: per image, lanes row-major, a lane's bands in order
+    lanes = []  # (image, lane row, lane column, bands)
+    base = 0
+    bands_of = lambda h: -(-h // 16)  # noqa: E731
+    image_order = {}
+    for k, (H, W) in enumerate(shapes):
+        ph, pw = min(patch[0], H), min(patch[1], W)
+        nly, nlx = -(-H // ph), -(-W // pw)
+        for ly in range(nly):
+            hl = min(ph, H - ly * ph)
+            for lx in range(nlx):
+                for bb in range(bands_of(hl)):
+                    image_order[(k, ly, lx, bb)] = base + ly * nlx * bands_of(ph) + lx * bands_of(hl) + bb
+        base += (nly - 1) * nlx * bands_of(ph) + nlx * bands_of(H - (nly - 1) * ph)
+    assert plan.n_bands == base == len(image_order)
+    want = [image_order[key] for key in sorted(image_order, key=lambda t: (t[3], t[0], t[1], t[2]))]
+    got = ws[plan.band_order_offset:plan.band_order_offset + 4 * plan.n_bands].cpu().numpy().view("<i4").tolist()
+    assert got == want
+    st = torch.empty(len(ts), dtype=torch.int32, device="cuda")
+    m.decode_run(plan, data, offs, st, ws)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0 and all(torch.equal(a, b) for a, b in zip(outs, ts))
