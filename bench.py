@@ -35,8 +35,8 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # 256 MiB device copy, per decoder layout; valid only for the kernel sources,
 # patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "sheared": {"src_sha": "661094df69ed3361", "patch": (86, 64), "interleave": 16,
-                "fetch_kib": 34089.6, "write_kib": 718453.3, "fetch_scale": 1.99982, "write_scale": 1.0},
+    "sheared": {"src_sha": "57c4b5dd8e658404", "patch": (82, 64), "interleave": 16,
+                "fetch_kib": 37672.8, "write_kib": 734319.1, "fetch_scale": 1.99982, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
@@ -694,7 +694,7 @@ def main():
     if os.path.exists(tpath):
         with open(tpath, "rb") as f:
             models_pc["B_trained"] = nx.Model(f.read())
-    layouts = {"whole": None, f"{ph}x{pw}": patch, "64x64": (64, 64), "32x32": (32, 32)}
+    layouts = {"whole": None, f"{ph}x{pw}": patch, "86x64": (86, 64), "64x64": (64, 64), "32x32": (32, 32)}
     wl = {"large6": ts, "uneven64": [torch.from_numpy(i).to(dev) for i in synth.workload_images("uneven64")]}
     for mname, mm in models_pc.items():
         for wname, wts in wl.items():

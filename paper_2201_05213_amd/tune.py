@@ -45,7 +45,7 @@ def image_streams(H: int, W: int, patch, interleave: int) -> int:
 
 
 def balanced_patch(shapes, cols: int = 64, cus: int | None = None, lanes_per_simd: int = 2, min_rows: int = 64,
-                   min_tail: float = 0.5, interleave: int = 1, bits_per_dim: float | None = None,
+                   min_tail: float = 0.25, interleave: int = 1, bits_per_dim: float | None = None,
                    max_bits_cost: float = 1e-3):
     """The shortest patch (rows, cols) that puts at most `lanes_per_simd`
     lanes on any SIMD of the decoder's launch.
@@ -58,10 +58,10 @@ def balanced_patch(shapes, cols: int = 64, cus: int | None = None, lanes_per_sim
     64 columns a lane's 16-row group is full (64 / (h + 1) rows per step for
     h = 3). Heights below `min_rows` are not considered, nor heights whose
     last lane row of some image is shorter than `min_tail` of the patch (a
-    thin ragged lane pays the same stream cost for few pixels). Given the
-    expected `bits_per_dim`, heights whose full lane's `interleave` streams
-    cost more than `max_bits_cost` of the lane's bits are not considered
-    either."""
+    thin ragged lane pays the same stream cost for few pixels; with ~5 bits
+    per stream a quarter of a lane keeps it small). Given the expected
+    `bits_per_dim`, heights whose full lane's `interleave` streams cost more
+    than `max_bits_cost` of the lane's bits are not considered either."""
     if cus is None:
         import torch
 

@@ -371,7 +371,7 @@ def test_autotune_patch_and_streams(models, nx):
 def test_large6_full_size_in_bench_configuration(models, nx, patch):
     """The large-image workload at full size (4 x 1024^2 + 2 x 2048x1536),
     model B, wavefront order, 4 streams per lane, with the benchmark's
-    patches (64 columns, the height from tune.balanced_patch: 86 rows on 256
+    patches (64 columns, the height from tune.balanced_patch: 82 rows on 256
     CUs) and with 64x64 patches: exact round trip of all 10.5 M pixels;
     sampled lanes within 0.1% of the oracle's quantised ideal; the full CDF
     rows of a sampled lane within 1 count of the oracle's."""

@@ -8,7 +8,7 @@ input of the oracle comes from the library), codes the benchmark's
 workloads: 32x32 images as whole lanes (the 512-image batch), the uneven
 batch with 32x32 and 64x64 patches, and the large batch with 64x64 patches
 and with the benchmark's (64 columns, the height from tune.balanced_patch:
-86 rows on 256 CUs), with one and with four rANS streams per lane. Coded bits
+82 rows on 256 CUs), with one and with four rANS streams per lane. Coded bits
 (the lane payloads) are compared with the oracle's quantised ideal -sum
 log2(f / 2^16) of the same lanes (sampled lanes for the large images).
 
