@@ -1481,6 +1481,7 @@ __global__ void __launch_bounds__(ROW_WAVES * 64) k_decode_rows(DecArgs A) {
     if (Q >= A.n_bands) break;
     // the queue's order of the bands (start step, then image and lane), or image order
     const int64_t B = A.band_order ? (int64_t)uniform(A.band_order[Q]) : Q;
+    if (B < 0 || B >= A.n_bands) continue;  // only a damaged workspace: never decode out of range
     decode_band<H_, C_, TRACE>(A, w, xb, hb, cb, sh, B);
   }
 }
