@@ -325,8 +325,9 @@ struct TrainPlan {
   int64_t off_conv, off_blocks, off_head, bias_conv, bias_blocks, bias_head;
 };
 
-constexpr int TRAIN_MAX_BLOCKS = 4;      // 2 n_blocks 1x1 layers in one gradient launch
-constexpr int64_t TRAIN_CHUNK = 512;     // pixels per weight-gradient partial
+constexpr int TRAIN_MAX_BLOCKS = 4;      // the head's parts, the first layer and 2 n_blocks 1x1 layers in one gradient launch
+static_assert(2 * TRAIN_MAX_BLOCKS + 1 + WGRAD_HEAD_PARTS <= WGRAD_MAX_LAYERS, "gradient launch layer table too small");
+constexpr int64_t WGRAD_CHUNK_ALIGN = 16;   // weight-gradient chunks: whole 4-pixel K-steps of each of 4 waves
 
 int device_lds_limit() {
   int dev = 0, v = 0;
@@ -356,8 +357,18 @@ nellox_status train_plan(const int32_t* dims, int32_t n, int32_t H, int32_t W, T
   T.n = n; T.H = H; T.W = W; T.ntx = (W + 15) / 16;
   T.npx = (int64_t)n * H * W;
   T.ntiles = (int64_t)n * H * T.ntx;
-  T.chunk = TRAIN_CHUNK;
-  T.nchunks = (T.npx + T.chunk - 1) / T.chunk;
+  // pixels per weight-gradient partial: as many chunks per layer as make
+  // the launch (layer entries x chunks workgroups) fill the device's
+  // resident workgroup slots once, so that every workgroup runs at the same
+  // time and none is left for a second, mostly idle round
+  {
+    const int64_t layers = 2LL * nb + 1 + WGRAD_HEAD_PARTS;
+    const int64_t slots = std::max(1, wgrad_blocks_per_cu(Cp / 16, T.KP / 16)) * (int64_t)device_cus();
+    const int64_t per_layer = std::max<int64_t>(1, slots / layers);
+    const int64_t chunk = (T.npx + per_layer - 1) / per_layer;
+    T.chunk = std::max(WGRAD_CHUNK_ALIGN, (chunk + WGRAD_CHUNK_ALIGN - 1) / WGRAD_CHUNK_ALIGN * WGRAD_CHUNK_ALIGN);
+    T.nchunks = (T.npx + T.chunk - 1) / T.chunk;
+  }
   T.wfloats = weight_layout(h, Cp, nb).total;
   T.wTfloats = weightT_layout(Cp, nb).total;
   if (check_lds) {
@@ -922,19 +933,22 @@ nellox_status nellox_nll_bwd(const float* params, const int32_t dims[4], const u
   g.npx = T.npx; g.chunk = T.chunk; g.nchunks = T.nchunks; g.ngrad = T.ngrad;
   g.partial = (float*)(w8 + T.partial);
   const int64_t pc = T.npx * T.Cp;
-  // first layer: deltas of a_0, inputs = the causal taps
-  g.layer[0] = WgradLayer{a.delta, a.ctx, T.Cp, T.KP, T.off_conv, T.bias_conv};
-  e = launch_wgrad(T.Cp / 16, T.KP / 16, g, 1, s);
-  if (e != hipSuccess) return hip_fail(e, "first-layer gradient launch");
-  // 1x1 layers: layer l (W1 of block l/2 or W2) has delta l + 1 and input u_l
+  // one launch for every layer, the head's row parts first: their deltas
+  // are the head rows', their input the last block's output; the first
+  // layer's deltas are those of a_0, its inputs the causal taps; 1x1 layer l
+  // (W1 of block l / 2 or W2) has delta l + 1 and input u_l
+  int nl = 0;
+  constexpr int head_rows = 16 * HEAD_TILES / WGRAD_HEAD_PARTS;
+  for (int q = 0; q < WGRAD_HEAD_PARTS; ++q)
+    g.layer[nl++] = WgradLayer{a.dtheta + q * head_rows, a.u + 2LL * T.nb * pc, 16 * HEAD_TILES, T.Cp,
+                               T.off_head + (int64_t)q * head_rows * T.Cp, T.bias_head + q * head_rows, WGRAD_HEAD};
+  g.layer[nl++] = WgradLayer{a.delta, a.ctx, T.Cp, T.KP, T.off_conv, T.bias_conv, WGRAD_FIRST};
   for (int l = 0; l < 2 * T.nb; ++l)
-    g.layer[l] = WgradLayer{a.delta + (l + 1) * pc, a.u + l * pc, T.Cp, T.Cp, T.off_blocks + (int64_t)l * T.Cp * T.Cp,
-                            T.bias_blocks + (int64_t)l * T.Cp};
-  e = launch_wgrad(T.Cp / 16, T.Cp / 16, g, 2 * T.nb, s);
-  if (e != hipSuccess) return hip_fail(e, "block gradient launch");
-  g.layer[0] = WgradLayer{a.dtheta, a.u + 2LL * T.nb * pc, 16 * HEAD_TILES, T.Cp, T.off_head, T.bias_head};
-  e = launch_wgrad(HEAD_TILES, T.Cp / 16, g, 1, s);
-  if (e != hipSuccess) return hip_fail(e, "head gradient launch");
+    g.layer[nl++] = WgradLayer{a.delta + (l + 1) * pc, a.u + l * pc, T.Cp, T.Cp,
+                               T.off_blocks + (int64_t)l * T.Cp * T.Cp, T.bias_blocks + (int64_t)l * T.Cp,
+                               WGRAD_BLOCK};
+  e = launch_wgrad(T.Cp / 16, T.KP / 16, g, nl, s);
+  if (e != hipSuccess) return hip_fail(e, "weight gradient launch");
   GradReduceArgs r{};
   r.h = T.h; r.C = T.C; r.Cp = T.Cp; r.nb = T.nb; r.KP = T.KP;
   r.off_conv = T.off_conv; r.off_blocks = T.off_blocks; r.off_head = T.off_head;

@@ -108,15 +108,24 @@ struct TrainArgs {
   const float* grad_bits;  // [n] d loss / d bits of image n
 };
 
+// layer kinds of the weight-gradient launch (they set the layer's shape)
+constexpr int WGRAD_FIRST = 0, WGRAD_BLOCK = 1, WGRAD_HEAD = 2;
+// the head's rows go to WGRAD_HEAD_PARTS layer entries (HEAD_TILES /
+// WGRAD_HEAD_PARTS row tiles each), which keeps every layer's accumulators
+// at most 4 row tiles wide
+constexpr int WGRAD_HEAD_PARTS = 2;
+constexpr int WGRAD_MAX_LAYERS = 11;  // the head's parts, first layer, up to 8 1x1 layers
+
 struct WgradLayer {
-  const float* delta;      // [npx][ld_delta]
-  const float* in;         // [npx][ld_in]
+  const float* delta;      // [npx][ld_delta], rows 16-byte aligned
+  const float* in;         // [npx][ld_in], rows 16-byte aligned
   int ld_delta, ld_in;
   int64_t w_off, b_off;    // offsets of this layer's dW [rows][cols] and db in a partial
+  int kind;                // WGRAD_FIRST, WGRAD_BLOCK or WGRAD_HEAD
 };
 
 struct WgradArgs {
-  WgradLayer layer[8];     // indexed by blockIdx.y
+  WgradLayer layer[WGRAD_MAX_LAYERS];  // indexed by blockIdx.y
   int64_t npx, chunk, nchunks, ngrad;
   float* partial;          // [nchunks][ngrad]
 };
@@ -172,7 +181,9 @@ hipError_t launch_swizzle(const float* params, int h, int C, int Cp, int nb, flo
                           int64_t nwT, hipStream_t s);
 hipError_t launch_train_fwd(int h, int Cp, const TrainArgs& a, int grid, hipStream_t s);
 hipError_t launch_train_bwd(int h, int Cp, const TrainArgs& a, int grid, hipStream_t s);
-hipError_t launch_wgrad(int MO, int KI, const WgradArgs& a, int nlayers, hipStream_t s);
+hipError_t launch_wgrad(int CT, int KT, const WgradArgs& a, int nlayers, hipStream_t s);
+// resident workgroups of that launch per CU (0 if the runtime cannot tell)
+int wgrad_blocks_per_cu(int CT, int KT);
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t s);
 hipError_t launch_bits_img(const float* bits, int n, int64_t per_img, double* out, hipStream_t s);
 

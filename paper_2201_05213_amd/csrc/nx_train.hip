@@ -7,8 +7,9 @@
 //                  saves the conv inputs, every layer input and the head rows
 //   k_train_bwd    per tile: d bits / d head rows (mixture backward), then the
 //                  deltas of every layer through the transposed weights
-//   k_wgrad        per (layer, pixel chunk): dW = sum_px delta (x) input and
-//                  db = sum_px delta on MFMA, one partial per chunk
+//   k_wgrad        per (layer, pixel chunk), every layer in one launch:
+//                  dW = sum_px delta (x) input and db = sum_px delta on
+//                  MFMA, one partial per chunk
 //   k_grad_reduce  sums the chunk partials in a fixed order into the
 //                  parameter vector's layout (deterministic)
 //   k_bits_img     per image: sum of per-pixel bits in FP64
@@ -18,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "nx_device.hpp"
 #include "nx_kernels.hpp"
@@ -294,29 +296,99 @@ __global__ void __launch_bounds__(TRAIN_WAVES * 64) k_train_bwd(TrainArgs A) {
 }
 
 // ------------------------------------------------------------------ weight gradients
-// One workgroup per (layer, chunk of pixels): D[row][col] = sum_px
-// delta[px][row] in[px][col] on v_mfma_f32_16x16x4f32 with K = 4 pixels per
-// instruction (A[i][k] = delta of pixel k, B[k][j] = input of pixel k), and
-// the bias gradient sum_px delta[px][row] from the same A values. The chunk
-// is split over WGRAD_WAVES waves (consecutive pixel ranges), each loading
-// the next four pixels' operands while its MFMAs run on the current ones;
-// their sums are added in LDS in wave order, so the result does not depend
-// on timing.
+// One launch for every layer: one workgroup per (layer, chunk of pixels)
+// computes D[row][col] = sum_px delta[px][row] in[px][col] on
+// v_mfma_f32_16x16x4f32 with K = 4 pixels per instruction (A[i][k] = delta of
+// pixel k, B[k][j] = input of pixel k), and the bias gradient
+// sum_px delta[px][row] from the same A values.
+//
+// Operand rows come in with 16-byte loads: for a width of 16 T channels, lane
+// (i, k) loads channels 64 b + 4 i .. 64 b + 4 i + 3 of its pixel for each
+// 64-channel block b < T / 4, and they feed tiles 4 b .. 4 b + 3 (tile 4 b + u
+// row i is channel 64 b + 4 i + u); the tiles past 4 (T / 4) take channel
+// 16 t + i with one 4-byte load. So a wave instruction reads four pixels' 256
+// contiguous bytes, and the output is mapped back to channels when stored.
+//
+// The chunk's K-steps go to the WGRAD_WAVES waves in turn. Each wave streams
+// its operands through a ring of WGRAD_DEPTH + 1 K-step slots
+// in LDS with direct global-to-LDS loads, WGRAD_DEPTH K-steps ahead of its
+// MFMAs, so the loads in flight cost no registers; it waits for a slot with
+// an explicit vmcnt (the compiler does not track these loads' LDS writes)
+// and refills the slot it read one step earlier, whose LDS reads are known to
+// be complete. The waves' sums are added in LDS in wave order, one row tile
+// at a time, so the result does not depend on timing.
 constexpr int WGRAD_WAVES = 4;
-constexpr int WGRAD_STEP = 8;  // pixels per prefetch (two MFMA K-steps of 4)
+constexpr int WGRAD_DEPTH = 7;  // K-steps (4 pixels each) in flight per wave
+
+// LDS floats of one K-step slot of an MO x KI layer: its delta, then its input
+constexpr int wgrad_slot(int MO, int KI) { return (MO + KI) * 64; }
+
+// s_waitcnt immediate that waits until at most n vector memory operations
+// are outstanding (expcnt and lgkmcnt left alone)
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// channel of row r of tile t of a 16 T-wide operand, as the loads place it
+NXD int op_channel(int T, int t, int r) {
+  return t < 4 * (T / 4) ? 64 * (t >> 2) + 4 * r + (t & 3) : 16 * t + r;
+}
+
+// tile and row holding channel c (inverse of op_channel)
+NXD void op_tile(int T, int c, int& t, int& r) {
+  if (c < 64 * (T / 4)) {
+    t = 4 * (c >> 6) + (c & 3);
+    r = (c & 63) >> 2;
+  } else {
+    t = c >> 4;
+    r = c & 15;
+  }
+}
+
+#define NX_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// direct loads of the T operand values of lane l = (i, k) for the pixel row
+// at base + row (base wave-uniform, row a 32-bit offset in floats) into the
+// LDS block dst (wave-uniform): the 16-byte parts first (lane l's four
+// channels of block b at dst + 256 b + 4 l), then the 4-byte parts (tile t
+// at dst + 256 (T / 4) + 64 (t - 4 (T / 4)) + l)
+template <int T>
+NXD void op_issue(const float* __restrict__ base, uint32_t row, int i, float* dst) {
+#pragma unroll
+  for (int b = 0; b < T / 4; ++b)
+    __builtin_amdgcn_global_load_lds(base + (row + 64 * b + 4 * i), NX_LDS(dst + 256 * b), 16, 0, 0);
+#pragma unroll
+  for (int t = 4 * (T / 4); t < T; ++t)
+    __builtin_amdgcn_global_load_lds(base + (row + 16 * t + i), NX_LDS(dst + 256 * (T / 4) + 64 * (t - 4 * (T / 4))),
+                                     4, 0, 0);
+}
+
+// load instructions per operand block of op_issue
+constexpr int op_loads(int T) { return T / 4 + T % 4; }
+
+// lane l's T operand values from an LDS block written by op_issue
+template <int T>
+NXD void op_read(const float* src, int lane, float (&v)[T]) {
+#pragma unroll
+  for (int b = 0; b < T / 4; ++b) {
+    const f4 x = *reinterpret_cast<const f4*>(src + 256 * b + 4 * lane);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[4 * b + u] = x[u];
+  }
+#pragma unroll
+  for (int t = 4 * (T / 4); t < T; ++t) v[t] = src[256 * (T / 4) + 64 * (t - 4 * (T / 4)) + lane];
+}
 
 template <int MO, int KI>
-__global__ void __launch_bounds__(WGRAD_WAVES * 64) k_wgrad(WgradArgs A) {
-  extern __shared__ float4 wg_smem[];
-  const WgradLayer Lr = A.layer[blockIdx.y];
+NXD void wgrad_layer(const WgradArgs& A, const WgradLayer& Lr, float* sm) {
   const int64_t c = blockIdx.x;
   const int64_t cl = c * A.chunk;
   const int64_t ch = cl + A.chunk < A.npx ? cl + A.chunk : A.npx;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
-  // this wave's pixels: a quarter of the chunk, a multiple of WGRAD_STEP long
-  const int64_t part = ((A.chunk + WGRAD_WAVES - 1) / WGRAD_WAVES + WGRAD_STEP - 1) / WGRAD_STEP * WGRAD_STEP;
-  const int64_t px_lo = cl + wv * part < ch ? cl + wv * part : ch;
-  const int64_t px_hi = px_lo + part < ch ? px_lo + part : ch;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar loop bounds
+  const int lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
+  // the chunk's K-steps (4 pixels each) go to the waves in turn: wave w
+  // takes K-steps w, w + 4, ..., so the workgroup reads its rows front to
+  // back as one stream
+  const int nk = (int)((ch - cl + 3) / 4);
+  const int nsteps = nk > wv ? (nk - wv + WGRAD_WAVES - 1) / WGRAD_WAVES : 0;
   f4 acc[MO][KI];
   float bacc[MO];
 #pragma unroll
@@ -325,84 +397,115 @@ __global__ void __launch_bounds__(WGRAD_WAVES * 64) k_wgrad(WgradArgs A) {
 #pragma unroll
     for (int kt = 0; kt < KI; ++kt) acc[mt][kt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   }
-  // operands of pixels px0 + 4 s + k, s = 0, 1 (rows past the range read as 0)
-  float a[2][MO], bv[2][KI];
-  auto fetch = [&](int64_t px0, float (&fa)[2][MO], float (&fb)[2][KI]) {
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      const int64_t pk = px0 + 4 * st + k;
-      const bool ok = pk < px_hi;
-      const int64_t pc = ok ? pk : cl;
-#pragma unroll
-      for (int mt = 0; mt < MO; ++mt) fa[st][mt] = ok ? Lr.delta[pc * Lr.ld_delta + 16 * mt + i] : 0.0f;
-#pragma unroll
-      for (int kt = 0; kt < KI; ++kt) fb[st][kt] = ok ? Lr.in[pc * Lr.ld_in + 16 * kt + i] : 0.0f;
-    }
+  // this wave's step st holds pixels cl + 4 (4 st + w) + k (past the chunk:
+  // its first pixel's rows, zeroed once read); addresses are the chunk's
+  // first rows (wave-uniform) plus 32-bit offsets
+  constexpr int SLOT = wgrad_slot(MO, KI), RING = WGRAD_DEPTH + 1, L = op_loads(MO) + op_loads(KI);
+  float* ring = sm + wv * RING * SLOT;
+  const float* __restrict__ dbase = Lr.delta + cl * Lr.ld_delta;
+  const float* __restrict__ ibase = Lr.in + cl * Lr.ld_in;
+  const uint32_t ldd = (uint32_t)Lr.ld_delta, ldi = (uint32_t)Lr.ld_in;
+  const int64_t span = ch - cl;
+  auto issue = [&](int st) {
+    int64_t p = 4 * (WGRAD_WAVES * (int64_t)st + wv) + k;
+    if (p >= span) p = 0;
+    const uint32_t rp = (uint32_t)p;
+    float* slot = ring + (st % RING) * SLOT;
+    op_issue<MO>(dbase, rp * ldd, i, slot);
+    op_issue<KI>(ibase, rp * ldi, i, slot + MO * 64);
   };
-  if (px_lo < px_hi) fetch(px_lo, a, bv);
-  for (int64_t px0 = px_lo; px0 < px_hi; px0 += WGRAD_STEP) {
-    float na[2][MO], nb[2][KI];
-    const bool more = px0 + WGRAD_STEP < px_hi;
-    if (more) fetch(px0 + WGRAD_STEP, na, nb);
+  for (int st = 0; st < nsteps && st < WGRAD_DEPTH; ++st) issue(st);
+  for (int st = 0; st < nsteps; ++st) {
+    // step st's loads are the oldest outstanding: wait for them, and only
+    // them while the ring is full
+    if (st + WGRAD_DEPTH <= nsteps)
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(L * (WGRAD_DEPTH - 1)));
+    else
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");  // the LDS reads stay after the wait
+    float fa[MO], fb[KI];
+    const float* slot = ring + (st % RING) * SLOT;
+    op_read<MO>(slot, lane, fa);
+    op_read<KI>(slot + MO * 64, lane, fb);
+    const int64_t p0 = 4 * (WGRAD_WAVES * (int64_t)st + wv);
+    if (p0 + 4 > span) {
+      const bool ok = p0 + k < span;
 #pragma unroll
-    for (int st = 0; st < 2; ++st)
+      for (int mt = 0; mt < MO; ++mt) fa[mt] = ok ? fa[mt] : 0.0f;
 #pragma unroll
-      for (int mt = 0; mt < MO; ++mt) {
-        bacc[mt] += a[st][mt];
-#pragma unroll
-        for (int kt = 0; kt < KI; ++kt)
-          acc[mt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st][mt], bv[st][kt], acc[mt][kt], 0, 0, 0);
-      }
-    if (more) {
-#pragma unroll
-      for (int st = 0; st < 2; ++st) {
-#pragma unroll
-        for (int mt = 0; mt < MO; ++mt) a[st][mt] = na[st][mt];
-#pragma unroll
-        for (int kt = 0; kt < KI; ++kt) bv[st][kt] = nb[st][kt];
-      }
+      for (int kt = 0; kt < KI; ++kt) fb[kt] = ok ? fb[kt] : 0.0f;
     }
-  }
-  // every wave parks its sums in LDS: value e of lane l at sm[(w PER + e) 64 + l]
-  constexpr int PER = MO * KI * 4 + MO;  // floats per lane
-  float* sm = (float*)wg_smem;
-  {
-    float* dst = sm + (int64_t)wv * PER * 64 + lane;
+    // refill the slot read one step ago (its LDS reads have completed: their
+    // values fed that step's MFMAs)
+    if (st + WGRAD_DEPTH < nsteps) issue(st + WGRAD_DEPTH);
 #pragma unroll
     for (int mt = 0; mt < MO; ++mt) {
+      bacc[mt] += fa[mt];
 #pragma unroll
       for (int kt = 0; kt < KI; ++kt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dst[((mt * KI + kt) * 4 + v) * 64] = acc[mt][kt][v];
-      dst[(MO * KI * 4 + mt) * 64] = bacc[mt];
+        acc[mt][kt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[mt], fb[kt], acc[mt][kt], 0, 0, 0);
     }
   }
+  // the rings are reused below for the waves' sums
   __syncthreads();
-  // the workgroup adds the waves' values in wave order, one (value, lane) per
-  // thread at a time, and writes the partials
+  // per row tile mt: every wave parks its values in LDS (value e of lane l at
+  // sm[(w E + e) 64 + l], e = 4 kt + v for the MFMA sums, e = 4 KI for the
+  // bias), then the workgroup adds the waves in wave order and writes the
+  // tile's 16 rows of the partial, a whole row of columns per 16 N threads
+  constexpr int E = 4 * KI + 1, N = 16 * KI;
   float* out = A.partial + c * A.ngrad;
-  const int N = 16 * KI;
-  for (int q = threadIdx.x; q < MO * KI * 4 * 64; q += WGRAD_WAVES * 64) {
-    const int e = q >> 6, l = q & 63;
-    float sum = sm[e * 64 + l];
 #pragma unroll
-    for (int w = 1; w < WGRAD_WAVES; ++w) sum = sum + sm[((int64_t)w * PER + e) * 64 + l];
-    const int v = e & 3, kt = (e >> 2) % KI, mt = (e >> 2) / KI;
-    const int li = l & 15, lk = l >> 4;
-    out[Lr.w_off + (int64_t)(16 * mt + 4 * lk + v) * N + 16 * kt + li] = sum;
-  }
-  // bias: per mt, lanes (i, k) hold partial sums over their pixels k; add the
-  // waves in order, then the four k groups as grp_sum does
-  if (wv == 0) {
+  for (int mt = 0; mt < MO; ++mt) {
+    if (mt > 0) __syncthreads();
+    float* dst = sm + (int64_t)wv * E * 64 + lane;
 #pragma unroll
-    for (int mt = 0; mt < MO; ++mt) {
-      float b = sm[(MO * KI * 4 + mt) * 64 + lane];
+    for (int kt = 0; kt < KI; ++kt)
 #pragma unroll
-      for (int w = 1; w < WGRAD_WAVES; ++w) b = b + sm[((int64_t)w * PER + MO * KI * 4 + mt) * 64 + lane];
-      const float bs = grp_sum(b);
-      if (k == 0) out[Lr.b_off + 16 * mt + i] = bs;
+      for (int v = 0; v < 4; ++v) dst[(4 * kt + v) * 64] = acc[mt][kt][v];
+    dst[4 * KI * 64] = bacc[mt];
+    __syncthreads();
+    for (int q = threadIdx.x; q < 16 * N + 16; q += WGRAD_WAVES * 64) {
+      if (q < 16 * N) {
+        // D[r][j] of tile (mt, kt) sits in value r & 3 of lane j + 16 (r >> 2)
+        const int r = q / N, col = q - r * N;
+        int kt, j;
+        op_tile(KI, col, kt, j);
+        const int e = 4 * kt + (r & 3), l = j + 16 * (r >> 2);
+        float sum = sm[e * 64 + l];
+#pragma unroll
+        for (int w = 1; w < WGRAD_WAVES; ++w) sum = sum + sm[(w * E + e) * 64 + l];
+        out[Lr.w_off + (int64_t)op_channel(MO, mt, r) * N + col] = sum;
+      } else {
+        // bias of row r: the waves in order, then the four pixel groups
+        const int r = q - 16 * N;
+        float bs = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          float b = sm[(4 * KI) * 64 + r + 16 * g];
+#pragma unroll
+          for (int w = 1; w < WGRAD_WAVES; ++w) b = b + sm[(w * E + 4 * KI) * 64 + r + 16 * g];
+          bs = g == 0 ? b : bs + b;
+        }
+        out[Lr.b_off + op_channel(MO, mt, r)] = bs;
+      }
     }
   }
+}
+
+// CT = C / 16 and KT = KP / 16 tiles; the layer's kind picks its shape:
+// (CT, KT) for the first layer, (CT, CT) for the 1x1 layers,
+// (HEAD_TILES / WGRAD_HEAD_PARTS, CT) for a part of the head
+template <int CT, int KT>
+__global__ void __launch_bounds__(WGRAD_WAVES * 64) k_wgrad(WgradArgs A) {
+  extern __shared__ float4 wg_smem[];
+  float* sm = (float*)wg_smem;
+  const WgradLayer Lr = A.layer[blockIdx.y];
+  if (Lr.kind == WGRAD_HEAD)
+    wgrad_layer<HEAD_TILES / WGRAD_HEAD_PARTS, CT>(A, Lr, sm);
+  else if (Lr.kind == WGRAD_FIRST)
+    wgrad_layer<CT, KT>(A, Lr, sm);
+  else
+    wgrad_layer<CT, CT>(A, Lr, sm);
 }
 
 // gradient of parameter idx (blob order) = sum over chunks of its partial
@@ -519,25 +622,57 @@ hipError_t launch_train_bwd(int h, int Cp, const TrainArgs& a, int grid, hipStre
   NX_TRAIN_DISPATCH(train_bwd_t, h, Cp, a, grid, s);
 }
 
-template <int MO, int KI>
+// LDS of the weight-gradient kernel: every wave's ring of K-step slots, or
+// one row tile's values of every wave, for the widest layer
+static size_t wgrad_lds(int CT, int KT) {
+  const int slot = std::max({wgrad_slot(CT, KT), wgrad_slot(CT, CT), wgrad_slot(HEAD_TILES / WGRAD_HEAD_PARTS, CT)});
+  const size_t ring = (size_t)WGRAD_WAVES * (WGRAD_DEPTH + 1) * slot;
+  const size_t sums = (size_t)WGRAD_WAVES * (4 * std::max(KT, CT) + 1) * 64;
+  return std::max(ring, sums) * sizeof(float);
+}
+
+// (asked of the runtime once per shape; 0 is not kept, so a query made
+// before a device is usable is repeated)
+template <int CT, int KT>
+static int wgrad_occupancy() {
+  static std::atomic<int> known{0};
+  int n = known.load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  if (allow_lds_t(k_wgrad<CT, KT>, wgrad_lds(CT, KT)) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wgrad<CT, KT>, WGRAD_WAVES * 64, wgrad_lds(CT, KT)) !=
+      hipSuccess)
+    return 0;
+  if (n > 0) known.store(n, std::memory_order_relaxed);
+  return n;
+}
+
+int wgrad_blocks_per_cu(int CT, int KT) {
+#define NX_WG(ct, kt) if (CT == ct && KT == kt) return wgrad_occupancy<ct, kt>()
+  NX_WG(1, 1); NX_WG(1, 3); NX_WG(1, 5);
+  NX_WG(2, 1); NX_WG(2, 3); NX_WG(2, 5);
+  NX_WG(4, 1); NX_WG(4, 3); NX_WG(4, 5);
+#undef NX_WG
+  return 0;
+}
+
+template <int CT, int KT>
 static hipError_t wgrad_t(const WgradArgs& a, int nlayers, hipStream_t s) {
-  const size_t lds = (size_t)WGRAD_WAVES * (MO * KI * 4 + MO) * 64 * sizeof(float);
-  hipError_t e = allow_lds_t(k_wgrad<MO, KI>, lds);
+  const size_t lds = wgrad_lds(CT, KT);
+  hipError_t e = allow_lds_t(k_wgrad<CT, KT>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_wgrad<MO, KI>), dim3((unsigned)a.nchunks, (unsigned)nlayers), dim3(WGRAD_WAVES * 64), lds, s,
+  hipLaunchKernelGGL((k_wgrad<CT, KT>), dim3((unsigned)a.nchunks, (unsigned)nlayers), dim3(WGRAD_WAVES * 64), lds, s,
                      a);
   return hipGetLastError();
 }
 
-// shapes in 16-wide tiles: (rows, cols) = (C/16, KP/16) for the first layer,
-// (C/16, C/16) for the 1x1 layers, (8, C/16) for the head
-hipError_t launch_wgrad(int MO, int KI, const WgradArgs& a, int nlayers, hipStream_t s) {
+// CT = C / 16 channel tiles, KT = KP / 16 first-layer input tiles
+hipError_t launch_wgrad(int CT, int KT, const WgradArgs& a, int nlayers, hipStream_t s) {
   if (nlayers == 0 || a.nchunks == 0) return hipSuccess;
-#define NX_WG(mo, ki) if (MO == mo && KI == ki) return wgrad_t<mo, ki>(a, nlayers, s)
-  NX_WG(1, 1); NX_WG(1, 2); NX_WG(1, 3); NX_WG(1, 5);
-  NX_WG(2, 1); NX_WG(2, 2); NX_WG(2, 3); NX_WG(2, 5);
-  NX_WG(4, 1); NX_WG(4, 3); NX_WG(4, 4); NX_WG(4, 5);
-  NX_WG(8, 1); NX_WG(8, 2); NX_WG(8, 4);
+  if (nlayers > WGRAD_MAX_LAYERS) return hipErrorInvalidValue;
+#define NX_WG(ct, kt) if (CT == ct && KT == kt) return wgrad_t<ct, kt>(a, nlayers, s)
+  NX_WG(1, 1); NX_WG(1, 3); NX_WG(1, 5);
+  NX_WG(2, 1); NX_WG(2, 3); NX_WG(2, 5);
+  NX_WG(4, 1); NX_WG(4, 3); NX_WG(4, 5);
 #undef NX_WG
   return hipErrorInvalidValue;
 }
