@@ -175,11 +175,12 @@ template <int H_, int C_>
 __global__ void __launch_bounds__(TRAIN_WAVES * 64) k_train_fwd(TrainArgs A) {
   extern __shared__ float4 smem_f4[];
   float* w = (float*)smem_f4;
-  {
-    const int64_t n4 = A.wfloats >> 2;
-    for (int64_t i = threadIdx.x; i < n4; i += TRAIN_WAVES * 64) ((float4*)w)[i] = ((const float4*)A.wimg)[i];
-    __syncthreads();
-  }
+  // the weight image goes to LDS while the first tile's context is gathered;
+  // every wave passes the one barrier once, after its first gather or, with
+  // no tile, at the end
+  const int64_t n4 = A.wfloats >> 2;
+  for (int64_t i = threadIdx.x; i < n4; i += TRAIN_WAVES * 64) ((float4*)w)[i] = ((const float4*)A.wimg)[i];
+  bool synced = false;
   constexpr int KC = conv_chunks(H_);
   const int lane = threadIdx.x & 63, p = lane & 15, g = lane >> 4;
   const bool has2 = g < 2;
@@ -193,6 +194,10 @@ __global__ void __launch_bounds__(TRAIN_WAVES * 64) k_train_fwd(TrainArgs A) {
     const uint8_t* img = A.imgs + (int64_t)T.n * A.H * A.W * 3;
     float ctx[KC];
     gather<H_>(ctx, tc, img, A.W, 0, 0, A.H, A.W, T.y, T.x, T.active);
+    if (!synced) {
+      __syncthreads();
+      synced = true;
+    }
     if (T.active) {
       float* cd = A.ctx + T.pix * A.KP;
 #pragma unroll
@@ -213,6 +218,7 @@ __global__ void __launch_bounds__(TRAIN_WAVES * 64) k_train_fwd(TrainArgs A) {
     const float lp = mix_joint<false>(head, xv, has2, 0.0f, unused);
     if (T.active && g == 0) A.bits[T.pix] = -lp * kLog2e;
   }
+  if (!synced) __syncthreads();
 }
 
 NXD f4 elu_grad(const f4& d, const f4& u) {
