@@ -35,8 +35,8 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # 256 MiB device copy, per decoder layout; valid only for the kernel sources,
 # patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "sheared": {"src_sha": "aecc61e80e389d05", "patch": (82, 64), "interleave": 16,
-                "fetch_kib": 38673.8, "write_kib": 734811.5, "fetch_scale": 1.99982, "write_scale": 1.0},
+    "sheared": {"src_sha": "c40f7184e48e2886", "patch": (82, 64), "interleave": 16,
+                "fetch_kib": 37809.3, "write_kib": 736628.5, "fetch_scale": 1.99982, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
