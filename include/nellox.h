@@ -284,8 +284,9 @@ nellox_status nellox_nll_fwd_train(const float* params, const int32_t dims[4], c
 /* Backward: grad_params (device, overwritten) = sum_k grad_bits[k] *
  * d bits_k / d params, grad_bits: device, n floats. ws must still hold the
  * state of the last nellox_nll_fwd_train with the same params, dims and
- * images (no other call on ws in between). Deterministic: the same inputs
- * give the same bits. */
+ * images (no other call on ws in between): the activations and the weight
+ * images come from there. Deterministic: the same inputs give the same
+ * bits. */
 nellox_status nellox_nll_bwd(const float* params, const int32_t dims[4], const uint8_t* imgs, int32_t n, int32_t H,
                              int32_t W, const float* grad_bits, float* grad_params, void* ws, size_t ws_bytes,
                              void* stream);

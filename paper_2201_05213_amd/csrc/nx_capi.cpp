@@ -923,11 +923,10 @@ nellox_status nellox_nll_bwd(const float* params, const int32_t dims[4], const u
   if ((int64_t)ws_bytes < T.total) return fail(NELLOX_E_CAPACITY, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* w8 = (uint8_t*)ws;
-  hipError_t e = launch_swizzle(params, T.h, T.C, T.Cp, T.nb, (float*)(w8 + T.wimg), T.wfloats,
-                                (float*)(w8 + T.wimgT), T.wTfloats, s);
-  if (e != hipSuccess) return hip_fail(e, "weight image launch");
+  // the transposed weight image is the one the forward built from the same
+  // params (the workspace holds the forward's state)
   const TrainArgs a = train_args(T, imgs, w8, grad_bits);
-  e = launch_train_bwd(T.h, T.Cp, a, train_grid(T), s);
+  hipError_t e = launch_train_bwd(T.h, T.Cp, a, train_grid(T), s);
   if (e != hipSuccess) return hip_fail(e, "training backward launch");
   WgradArgs g{};
   g.npx = T.npx; g.chunk = T.chunk; g.nchunks = T.nchunks; g.ngrad = T.ngrad;
