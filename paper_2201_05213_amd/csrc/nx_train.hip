@@ -514,49 +514,70 @@ __global__ void __launch_bounds__(WGRAD_WAVES * 64) k_wgrad(WgradArgs A) {
     wgrad_layer<CT, CT>(A, Lr, sm);
 }
 
-// gradient of parameter idx (blob order) = sum over chunks of its partial
-__global__ void k_grad_reduce(GradReduceArgs A) {
-  const ParamLayout P = param_layout(A.h, A.C, A.nb);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// gradient of parameter idx (blob order) = sum over chunks of its partial.
+// A workgroup takes GR_PARAMS consecutive parameters; its GR_GROUPS thread
+// groups each add one contiguous range of chunks in chunk order (FP64), and
+// the ranges' sums are then added in range order, so the result does not
+// depend on timing.
+constexpr int GR_PARAMS = 64, GR_GROUPS = 4;
+
+NXD int64_t grad_source(const GradReduceArgs& A, const ParamLayout& P, int64_t idx) {
   const int K = 2 * A.h + 1, C = A.C, Cp = A.Cp;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < P.total; idx += stride) {
-    int64_t src = -1;
-    if (idx < P.conv_b) {
-      const int64_t o = idx / (3 * K * K), r = idx % (3 * K * K);
-      const int ch = (int)(r / (K * K)), dy = (int)((r / K) % K), dx = (int)(r % K);
-      const int t = tap_index(A.h, dy, dx);
-      if (t >= 0) src = A.off_conv + o * A.KP + 3 * t + ch;
-    } else if (idx < P.blocks) {
-      src = A.bias_conv + (idx - P.conv_b);
-    } else if (idx < P.head_w) {
-      const int64_t b = (idx - P.blocks) / P.block_stride, r = (idx - P.blocks) % P.block_stride;
-      const int64_t cc = (int64_t)C * C;
-      if (r < cc) src = A.off_blocks + (2 * b) * Cp * Cp + (r / C) * Cp + r % C;
-      else if (r < cc + C) src = A.bias_blocks + (2 * b) * Cp + (r - cc);
-      else if (r < 2 * cc + C) src = A.off_blocks + (2 * b + 1) * Cp * Cp + ((r - cc - C) / C) * Cp + (r - cc - C) % C;
-      else src = A.bias_blocks + (2 * b + 1) * Cp + (r - 2 * cc - C);
-    } else if (idx < P.head_b) {
-      const int64_t r = idx - P.head_w;
-      src = A.off_head + (int64_t)head_row_of((int)(r / C)) * Cp + r % C;
-    } else {
-      src = A.bias_head + head_row_of((int)(idx - P.head_b));
-    }
-    // chunk partials added in chunk order; loaded 16 at a time so that many
-    // loads are in flight
-    double s = 0.0;
-    if (src >= 0) {
-      const float* col = A.partial + src;
-      int64_t c = 0;
-      for (; c + 16 <= A.nchunks; c += 16) {
-        float v[16];
+  int64_t src = -1;
+  if (idx < P.conv_b) {
+    const int64_t o = idx / (3 * K * K), r = idx % (3 * K * K);
+    const int ch = (int)(r / (K * K)), dy = (int)((r / K) % K), dx = (int)(r % K);
+    const int t = tap_index(A.h, dy, dx);
+    if (t >= 0) src = A.off_conv + o * A.KP + 3 * t + ch;
+  } else if (idx < P.blocks) {
+    src = A.bias_conv + (idx - P.conv_b);
+  } else if (idx < P.head_w) {
+    const int64_t b = (idx - P.blocks) / P.block_stride, r = (idx - P.blocks) % P.block_stride;
+    const int64_t cc = (int64_t)C * C;
+    if (r < cc) src = A.off_blocks + (2 * b) * Cp * Cp + (r / C) * Cp + r % C;
+    else if (r < cc + C) src = A.bias_blocks + (2 * b) * Cp + (r - cc);
+    else if (r < 2 * cc + C) src = A.off_blocks + (2 * b + 1) * Cp * Cp + ((r - cc - C) / C) * Cp + (r - cc - C) % C;
+    else src = A.bias_blocks + (2 * b + 1) * Cp + (r - 2 * cc - C);
+  } else if (idx < P.head_b) {
+    const int64_t r = idx - P.head_w;
+    src = A.off_head + (int64_t)head_row_of((int)(r / C)) * Cp + r % C;
+  } else {
+    src = A.bias_head + head_row_of((int)(idx - P.head_b));
+  }
+  return src;
+}
+
+__global__ void __launch_bounds__(GR_PARAMS * GR_GROUPS) k_grad_reduce(GradReduceArgs A) {
+  __shared__ double part[GR_GROUPS][GR_PARAMS];
+  const ParamLayout P = param_layout(A.h, A.C, A.nb);
+  const int q = threadIdx.x % GR_PARAMS, g = threadIdx.x / GR_PARAMS;
+  const int64_t idx = (int64_t)blockIdx.x * GR_PARAMS + q;
+  const int64_t src = idx < P.total ? grad_source(A, P, idx) : -1;
+  const int64_t per = (A.nchunks + GR_GROUPS - 1) / GR_GROUPS;
+  const int64_t c0 = g * per < A.nchunks ? g * per : A.nchunks;
+  const int64_t c1 = c0 + per < A.nchunks ? c0 + per : A.nchunks;
+  // this group's chunks in order, loaded 8 at a time so that many loads are
+  // in flight
+  double s = 0.0;
+  if (src >= 0) {
+    const float* col = A.partial + src;
+    int64_t c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      float v[8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = col[(c + u) * A.ngrad];
+      for (int u = 0; u < 8; ++u) v[u] = col[(c + u) * A.ngrad];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += (double)v[u];
-      }
-      for (; c < A.nchunks; ++c) s += (double)col[c * A.ngrad];
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
     }
-    A.grad[idx] = (float)s;
+    for (; c < c1; ++c) s += (double)col[c * A.ngrad];
+  }
+  part[g][q] = s;
+  __syncthreads();
+  if (g == 0 && idx < P.total) {
+    double t = part[0][q];
+#pragma unroll
+    for (int r = 1; r < GR_GROUPS; ++r) t += part[r][q];
+    A.grad[idx] = (float)t;
   }
 }
 
@@ -685,8 +706,8 @@ hipError_t launch_wgrad(int CT, int KT, const WgradArgs& a, int nlayers, hipStre
 
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t s) {
   const ParamLayout P = param_layout(a.h, a.C, a.nb);
-  const int grid = (int)std::min<int64_t>((P.total + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_grad_reduce, dim3(grid), dim3(256), 0, s, a);
+  const int64_t grid = (P.total + GR_PARAMS - 1) / GR_PARAMS;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)grid), dim3(GR_PARAMS * GR_GROUPS), 0, s, a);
   return hipGetLastError();
 }
 
