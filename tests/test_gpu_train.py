@@ -148,6 +148,30 @@ def test_grad_model_B_training_batch(tr):
     compare(dims, params, crops(64, 32, 5_999_999), np.ones(64), tr, "model B 64x32x32")
 
 
+def test_grad_large_batch_is_sum_of_its_halves(tr):
+    """Linearity past the training batch, where the oracle would be slow: 96
+    synthetic 64x64 images (393,216 px, so the weight-gradient launch runs
+    long chunks) and the same images in two halves of 48. Each image's code
+    length is a sum over its own pixels, so the per-image bits must agree
+    bitwise; the weighted gradient of the whole batch must equal the sum of
+    the halves' gradients up to FP32 summation order, within
+    1e-4 |g| + 1e-5 max |g| per element."""
+    train, blob = tr
+    dims, params = model("B", blob)
+    imgs = synth.training_pool(n=96)
+    w = np.random.default_rng(17).uniform(0.5, 1.5, size=96)
+    say("[gpu] train: model B, 96 images 64x64 against its two halves")
+    b_all, g_all = gpu_bits_grad(train, dims, params, imgs, w)
+    b_lo, g_lo = gpu_bits_grad(train, dims, params, imgs[:48], w[:48])
+    b_hi, g_hi = gpu_bits_grad(train, dims, params, imgs[48:], w[48:])
+    assert np.array_equal(b_all, np.concatenate([b_lo, b_hi]))
+    g_sum = g_lo + g_hi
+    bound = GRAD_TOL * np.abs(g_sum) + 1e-5 * np.abs(g_sum).max()
+    worst = float((np.abs(g_all - g_sum) / bound).max())
+    say(f"  worst |diff| / bound {worst:.3f}")
+    assert worst <= 1.0
+
+
 def test_backward_is_deterministic(tr):
     say("[gpu] train: determinism")
     train, blob = tr
