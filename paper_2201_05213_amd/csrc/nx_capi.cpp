@@ -360,7 +360,7 @@ nellox_status train_plan(const int32_t* dims, int32_t n, int32_t H, int32_t W, T
   // pixels per weight-gradient partial: as many chunks per layer as make
   // the launch (layer entries x chunks workgroups) fill the device's
   // resident workgroup slots once, so that every workgroup runs at the same
-  // time and none is left for a second, mostly idle round
+  // time and none is left over to run alone on a mostly idle device
   {
     const int64_t layers = 2LL * nb + 1 + WGRAD_HEAD_PARTS;
     const int64_t slots = std::max(1, wgrad_blocks_per_cu(Cp / 16, T.KP / 16)) * (int64_t)device_cus();
