@@ -597,15 +597,35 @@ __global__ void __launch_bounds__(256) k_bits_img(const float* bits, int64_t per
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename K>
-static hipError_t allow_lds_t(K kernel, size_t lds) {
-  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+// Raises a kernel's dynamic LDS limit on the current device. The attribute
+// call is made again only when a launch needs more than the last call set,
+// so once a kernel has run outside a stream capture, launches inside one
+// make no such call.
+constexpr int MAX_DEVICES = 64;
+
+template <auto Kernel>
+static hipError_t allow_lds_t(size_t lds) {
+  static std::atomic<size_t> set[MAX_DEVICES];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) dev = -1;
+  if (dev >= 0 && lds <= set[dev].load(std::memory_order_relaxed)) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void*)Kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // reported here, not by the next launch's check
+    return e;
+  }
+  if (dev >= 0) {
+    size_t cur = set[dev].load(std::memory_order_relaxed);
+    while (cur < lds && !set[dev].compare_exchange_weak(cur, lds, std::memory_order_relaxed)) {
+    }
+  }
+  return hipSuccess;
 }
 
 template <int H_, int C_>
 static hipError_t train_fwd_t(const TrainArgs& a, int grid, hipStream_t s) {
   const size_t lds = (size_t)a.wfloats * 4;
-  hipError_t e = allow_lds_t(k_train_fwd<H_, C_>, lds);
+  hipError_t e = allow_lds_t<k_train_fwd<H_, C_>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_train_fwd<H_, C_>), dim3(grid), dim3(TRAIN_WAVES * 64), lds, s, a);
   return hipGetLastError();
@@ -614,7 +634,7 @@ static hipError_t train_fwd_t(const TrainArgs& a, int grid, hipStream_t s) {
 template <int H_, int C_>
 static hipError_t train_bwd_t(const TrainArgs& a, int grid, hipStream_t s) {
   const size_t lds = (size_t)a.wTfloats * 4;
-  hipError_t e = allow_lds_t(k_train_bwd<H_, C_>, lds);
+  hipError_t e = allow_lds_t<k_train_bwd<H_, C_>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_train_bwd<H_, C_>), dim3(grid), dim3(TRAIN_WAVES * 64), lds, s, a);
   return hipGetLastError();
@@ -665,7 +685,7 @@ static int wgrad_occupancy() {
   static std::atomic<int> known{0};
   int n = known.load(std::memory_order_relaxed);
   if (n > 0) return n;
-  if (allow_lds_t(k_wgrad<CT, KT>, wgrad_lds(CT, KT)) != hipSuccess) return 0;
+  if (allow_lds_t<k_wgrad<CT, KT>>(wgrad_lds(CT, KT)) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wgrad<CT, KT>, WGRAD_WAVES * 64, wgrad_lds(CT, KT)) !=
       hipSuccess)
     return 0;
@@ -685,7 +705,7 @@ int wgrad_blocks_per_cu(int CT, int KT) {
 template <int CT, int KT>
 static hipError_t wgrad_t(const WgradArgs& a, int nlayers, hipStream_t s) {
   const size_t lds = wgrad_lds(CT, KT);
-  hipError_t e = allow_lds_t(k_wgrad<CT, KT>, lds);
+  hipError_t e = allow_lds_t<k_wgrad<CT, KT>>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_wgrad<CT, KT>), dim3((unsigned)a.nchunks, (unsigned)nlayers), dim3(WGRAD_WAVES * 64), lds, s,
                      a);

@@ -172,6 +172,48 @@ def test_grad_large_batch_is_sum_of_its_halves(tr):
     assert worst <= 1.0
 
 
+def test_graph_replays_match_eager(tr):
+    """Forward and backward captured once in a HIP graph (torch.cuda.graph)
+    and replayed on new crops copied into its input buffer give bitwise the
+    bits and the gradient of eager calls on the same crops. Eager work and a
+    synchronisation run between the replays."""
+    train, blob = tr
+    dims, params = model("A", blob)
+    p = torch.from_numpy(params).cuda().requires_grad_(True)
+    batches = [torch.from_numpy(crops(8, 32, 100 + k)).cuda() for k in range(4)]
+    w = torch.linspace(0.5, 1.5, 8, dtype=torch.float64, device="cuda")
+
+    def eager(x):
+        q = p.detach().clone().requires_grad_(True)
+        bits = train.nll_bits(q, dims, x)
+        (bits * w).sum().backward()
+        return bits.detach().clone(), q.grad.detach().clone()
+
+    ref = [eager(x) for x in batches]
+    static_x = batches[0].clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            p.grad = None
+            (train.nll_bits(p, dims, static_x) * w).sum().backward()
+    torch.cuda.current_stream().wait_stream(side)
+    p.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        static_bits = train.nll_bits(p, dims, static_x)
+        (static_bits * w).sum().backward()
+    say("[gpu] train: graph captured, replaying")
+    for k in (1, 3, 0, 2):
+        static_x.copy_(batches[k])
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(static_bits, ref[k][0]), k
+        assert torch.equal(p.grad, ref[k][1]), k
+        eager(batches[(k + 1) % 4])
+        torch.cuda.synchronize()
+
+
 def test_backward_is_deterministic(tr):
     say("[gpu] train: determinism")
     train, blob = tr
