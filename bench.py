@@ -616,6 +616,51 @@ def main():
                      "frac_fp32_peak": tflops / PEAK_FP32,
                      "sample": "model B, 64 random 32x32 crops per step, forward + backward + Adam"}
         log(f"[bench] training step {tstep * 1e3:.3f} ms ({tflops / 1e12:.1f} TFLOP/s fwd+bwd)")
+        # the same step captured once as a HIP graph (torch.cuda.graph) and
+        # replayed on each batch copied into the graph's input buffer: the
+        # kernels are those of the eager step, without the host's launch gaps
+        try:
+            pg = torch.nn.Parameter(torch.from_numpy(tparams).to(dev))
+            optg = torch.optim.Adam([pg], lr=1e-3, fused=True, capturable=True)
+            sx = batches[0].clone()
+
+            def graph_body():
+                loss = nxtrain.nll_bits(pg, tdims, sx).sum() / sx.numel()
+                loss.backward()
+                optg.step()
+
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for _ in range(3):
+                    optg.zero_grad(set_to_none=True)
+                    graph_body()
+            torch.cuda.current_stream().wait_stream(side)
+            optg.zero_grad(set_to_none=True)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                graph_body()
+            for x in batches[:5]:
+                sx.copy_(x)
+                graph.replay()
+            torch.cuda.synchronize()
+            gs = torch.cuda.current_stream()
+            tg0, tg1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            tg0.record(gs)
+            for x in batches[5:]:
+                sx.copy_(x)
+                graph.replay()
+            tg1.record(gs)
+            torch.cuda.synchronize()
+            tgs = tg0.elapsed_time(tg1) / 1e3 / args.train_steps
+            train_rec["step_ms_graph"] = tgs * 1e3
+            train_rec["frac_fp32_peak_graph"] = 3 * flops_per_px * tpx / tgs / PEAK_FP32
+            log(f"[bench] training step as a replayed graph {tgs * 1e3:.3f} ms "
+                f"({3 * flops_per_px * tpx / tgs / 1e12:.1f} TFLOP/s fwd+bwd)")
+            del graph
+        except RuntimeError as e:
+            train_rec["step_ms_graph"] = None
+            log(f"[bench] training step graph capture failed: {e}")
 
     # the same workload coded by the trained model B (the 2000-step training
     # recipe, run on the CPU by the oracle; ~4.4 bits/dim here): decode time

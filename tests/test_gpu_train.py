@@ -214,6 +214,47 @@ def test_graph_replays_match_eager(tr):
         torch.cuda.synchronize()
 
 
+def test_graph_training_steps_match_eager(tr):
+    """Whole Adam steps (forward, backward, torch's fused Adam with
+    capturable state) captured once as a graph: after three eager warm-up
+    steps on a side stream and five replays on new crops, the parameters
+    equal bitwise those of eight eager steps on the same crops."""
+    train, blob = tr
+    dims, params = model("A", blob)
+    batches = [torch.from_numpy(crops(8, 32, 200 + k)).cuda() for k in range(8)]
+    p = torch.nn.Parameter(torch.from_numpy(params).cuda())
+    opt = torch.optim.Adam([p], lr=1e-3, fused=True)
+    for x in batches:
+        opt.zero_grad(set_to_none=True)
+        (train.nll_bits(p, dims, x).sum() / x.numel()).backward()
+        opt.step()
+    pg = torch.nn.Parameter(torch.from_numpy(params).cuda())
+    optg = torch.optim.Adam([pg], lr=1e-3, fused=True, capturable=True)
+    sx = batches[0].clone()
+
+    def body():
+        (train.nll_bits(pg, dims, sx).sum() / sx.numel()).backward()
+        optg.step()
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for x in batches[:3]:
+            sx.copy_(x)
+            optg.zero_grad(set_to_none=True)
+            body()
+    torch.cuda.current_stream().wait_stream(side)
+    optg.zero_grad(set_to_none=True)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        body()
+    for x in batches[3:]:
+        sx.copy_(x)
+        graph.replay()
+        torch.cuda.synchronize()
+    assert torch.equal(pg.detach(), p.detach())
+
+
 def test_backward_is_deterministic(tr):
     say("[gpu] train: determinism")
     train, blob = tr
