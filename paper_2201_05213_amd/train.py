@@ -11,6 +11,11 @@ tensor order; `blob.params_from_blob` / `blob.blob_from_params` convert.
     opt = torch.optim.Adam([p], lr=1e-3, fused=True)
     bits = nll_bits(p, dims, crops)          # crops: (N, H, W, 3) uint8 on the GPU
     (bits.sum() / crops[..., 0].numel() / 3).backward(); opt.step()
+
+A whole step (forward, backward and a capturable Adam) can be captured once
+with torch.cuda.graph and replayed on new crops copied into its input
+tensor: the library's calls make no host synchronisation and allocate
+through torch, and replays give bitwise the eager step's parameters.
 """
 from __future__ import annotations
 
