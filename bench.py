@@ -141,6 +141,10 @@ def main():
     ap.add_argument("--profile-rows", action="store_true",
                     help="only decode image 0 (1024^2) as a whole-image lane with row streams, warmup + steps "
                          "times (for profiler runs of the row-stream decoder; prints no JSON)")
+    ap.add_argument("--profile-train", action="store_true",
+                    help="only run warmup + steps training steps of the training leg (model B, 64 random 32x32 "
+                         "crops, forward + backward + Adam; for profiler runs of the training kernels; prints no "
+                         "JSON)")
     ap.add_argument("--profile", action="store_true",
                     help="time only the batch decode, then run the full-image pass and the encode three times "
                          "each and a known-size copy for counter calibration (for profiler runs; prints no "
@@ -158,6 +162,23 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.profile_train:
+        from paper_2201_05213_amd import blob as nxblob, train as nxtrain
+
+        tdims, tparams = nxblob.params_from_blob(synth.model_blob("B")[0])
+        pool = torch.from_numpy(synth.training_pool(n=512)).to(dev)
+        rng = np.random.Generator(np.random.PCG64(5_999_999))
+        p = torch.nn.Parameter(torch.from_numpy(tparams).to(dev))
+        opt = torch.optim.Adam([p], lr=1e-3, fused=True)
+        batches = [nxtrain.random_crops(pool, 64, 32, rng) for _ in range(args.warmup + args.steps)]
+        torch.cuda.synchronize()
+        for x in batches:
+            opt.zero_grad(set_to_none=True)
+            (nxtrain.nll_bits(p, tdims, x).sum() / x.numel()).backward()
+            opt.step()
+        torch.cuda.synchronize()
+        log(f"[bench] profile-train mode: {args.warmup + args.steps} training steps done")
+        return
     t0 = time.time()
     imgs = synth.workload_images("large6")
     log(f"[bench] generated {len(imgs)} images in {time.time() - t0:.1f}s")
