@@ -35,23 +35,24 @@ CALIB_BYTES = 256 << 20  # copy kernel used to calibrate the HBM byte counters
 # 256 MiB device copy, per decoder layout; valid only for the kernel sources,
 # patch shape and streams per lane they were taken on
 DECODE_TRAFFIC = {
-    "sheared": {"src_sha": "69572bd146496c6a", "patch": (82, 64), "interleave": 16,
+    "sheared": {"src_sha": "fd38217a5f6439eb", "patch": (82, 64), "interleave": 16,
                 "fetch_kib": 38035.7, "write_kib": 748684.8, "fetch_scale": 1.99982, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("nx_kernels.hip", "nx_device.hpp", "nx_layout.hpp", "nx_kernels.hpp", "nx_order.hpp")
 
 
 def kernel_sources_sha() -> str:
-    """sha256[:16] of the coder's kernel sources and of the build script
-    (its compiler flags shape the same kernels)."""
+    """sha256[:16] of the coder's kernel sources and of the compiler flags
+    they are built with."""
     import hashlib
+
+    from paper_2201_05213_amd import build as nxbuild
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2201_05213_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    with open(os.path.join(ROOT, "paper_2201_05213_amd", "build.py"), "rb") as fh:
-        h.update(fh.read())
+    h.update(repr(nxbuild.coder_flags()).encode())
     return h.hexdigest()[:16]
 
 

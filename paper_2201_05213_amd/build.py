@@ -27,7 +27,13 @@ HIPCC_FLAGS = [
 # flags of single sources: the coder's kernels are bound by SIMD issue, and
 # LLVM's iterative ILP scheduler orders their instructions with more overlap
 # than the default one (the arithmetic and its order are unchanged)
-SOURCE_FLAGS = {"nx_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
+SOURCE_FLAGS = {"nx_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+                "nx_train.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
+def coder_flags() -> list:
+    """The compiler flags of the coder's kernels (nx_kernels.hip)."""
+    return [f for f in HIPCC_FLAGS if f != "-shared"] + SOURCE_FLAGS["nx_kernels.hip"]
 
 
 def build(verbose: bool = False) -> str:
